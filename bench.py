@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the fluctuating non-ideal D3Q19 lattice-Boltzmann step on one GPU.
+
+Headline: million lattice-site updates per second (MLUPS) of the plain
+256^3 lattice (FP32 storage), every step being the whole hot path: pull,
+density halo, chemical potential, force, Philox noise, moment-space
+collision, store, and every 10th step the FP64 block moments and axis
+structure factor.  Inputs are synthetic (seeded initial density), resident in
+device memory before the timed region.
+
+Also reported on the same line:
+  roofline      the fused step kernel against the 8 TB/s HBM peak, with
+                152 algorithmic bytes per site update (19 FP32 populations
+                read + 19 written), timed with HIP events on its stream;
+  cpu_baseline  the FP64 oracle on a bounded sample of the same workload;
+  batched       the 96-replica finite-size sweep in one handle against the
+                same 96 replicas run one after another (same seeds and steps,
+                so the results are identical).
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SITE = {"fp32": 152, "fp16": 76}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1202_4748_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload, storage):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, or None if absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_k_fused_{workload}_{storage}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="d3q19_256")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--sample-every", type=int, default=10)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only run warmup + timed steps (for profiler runs)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the multi-GPU path (replica sharding, z-slab "
+              "halo exchange) is a design, not built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1202_4748_amd as lbf
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+
+    wl = dict(workloads.WORKLOADS[args.workload])
+    L = wl.pop("L")
+    wl.pop("steps")
+    wl.pop("storage", None)
+    N = L ** 3
+    log(f"[bench] {args.workload}: {L}^3, storage {args.storage}, sample every {args.sample_every}")
+    sim = lbf.Sim(L, workloads.SEED, storage=args.storage, sample_every=args.sample_every, **wl)
+    plan = sim.plan()
+    if not args.no_tune and not args.kernel_only:
+        plan = sim.tune(steps=10)
+        log(f"[bench] tuned plan {plan}")
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mlups = N * args.steps / dt / 1e6
+    log(f"[bench] {args.steps} steps in {dt:.3f} s: {mlups:.0f} MLUPS")
+    if args.kernel_only:
+        print(json.dumps({"metric": "MLUPS", "value": mlups, "steps": args.steps}))
+        return
+    mom = sim.moments()
+    mass_drift = None
+
+    # dominant kernel alone: same plan without sample steps, HIP events on its stream
+    kplan = dict(plan)
+    ksim = lbf.Sim(L, workloads.SEED, storage=args.storage, **wl)
+    ksim.set_plan("fused" if kplan["kernel"] == lbf.LB_KERNEL_FUSED else "split",
+                  (kplan["tile_x"], kplan["tile_y"], kplan["tile_z"]), max(kplan["graph_steps"], 20))
+    ksim.step(40)
+    ksim.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nk = max(ksim.plan()["graph_steps"], 20) * 10
+    e0.record(stream)
+    ksim.step(nk)
+    e1.record(stream)
+    e1.synchronize()
+    ms_per_launch = e0.elapsed_time(e1) / nk
+    algo_bytes = BYTES_PER_SITE[args.storage] * N
+    achieved = algo_bytes / (ms_per_launch * 1e-3) / 1e9
+    kname = "k_fused" if kplan["kernel"] == lbf.LB_KERNEL_FUSED else "k_collide"
+    log(f"[bench] {kname}: {ms_per_launch * 1e3:.1f} us per step, {achieved:.0f} GB/s algorithmic")
+    traffic = read_traffic(args.workload, args.storage)
+    del ksim
+
+    result = {
+        "metric": "MLUPS D3Q19 fluctuating step, % HBM roofline; batched vs plain at equal accuracy",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"plain D3Q19 {L}^3 ({args.workload})", "L": L, "sites": N,
+                   "storage": args.storage, "sample_every": args.sample_every,
+                   "params": {k: wl[k] for k in ("a", "b", "kappa", "rho_c", "kT", "tau")},
+                   "plan": plan},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_site": BYTES_PER_SITE[args.storage],
+                     "us_per_launch": round(ms_per_launch * 1e3, 2)},
+        "mass": mom["mass"],
+    }
+
+    if not args.no_batched:
+        result["batched"] = batched_vs_plain(lbf, workloads, torch)
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(L, wl)
+
+    print(json.dumps(result), flush=True)
+
+
+def batched_vs_plain(lbf, workloads, torch, steps=200):
+    """96 replicas of the finite-size sweep in one handle against the same
+    replicas advanced one handle at a time; identical seeds and steps, so
+    identical results (checked on two replicas)."""
+    import numpy as np
+    Ls, seeds, prms = workloads.sweep_replicas()
+    prms = [dict(p, sample_every=10, n_levels=2) for p in prms]
+    sites = sum(L ** 3 for L in Ls)
+    log(f"[bench] batched sweep: {len(Ls)} replicas, {sites} sites")
+    bat = lbf.Sim.batch(Ls, seeds, prms)
+    bat.tune(steps=10)
+    bplan = bat.plan()
+    t_before = bat.info()["step"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bat.step(steps)
+    bat.sync()
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    singles = []
+    for L, sd, p in zip(Ls, seeds, prms):
+        s = lbf.Sim(L, sd, **p)
+        s.set_plan("fused" if bplan["kernel"] == lbf.LB_KERNEL_FUSED else "split",
+                   (bplan["tile_x"], bplan["tile_y"], bplan["tile_z"]), bplan["graph_steps"])
+        singles.append(s)
+    for s in singles:  # same step count as the batch before its timed region
+        s.step(t_before)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in singles:
+        s.step(steps)
+    for s in singles:
+        s.sync()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    equal = True
+    for r in (0, len(Ls) - 1):
+        equal &= bool(np.array_equal(bat.fields(r, f=True)["f"], singles[r].fields(f=True)["f"]))
+    out = {"replicas": len(Ls), "sites": sites, "steps": steps,
+           "batched_mlups": round(sites * steps / t_bat / 1e6, 1),
+           "sequential_mlups": round(sites * steps / t_seq / 1e6, 1),
+           "speedup": round(t_seq / t_bat, 2), "identical_results": equal, "plan": bplan}
+    log(f"[bench] batched {out['batched_mlups']} MLUPS vs sequential {out['sequential_mlups']} "
+        f"MLUPS: x{out['speedup']}")
+    return out
+
+
+def cpu_baseline(L, wl):
+    """The FP64 oracle timed on the host cores on one step of the same lattice."""
+    import oracle
+    threads = oracle.default_threads()
+    log(f"[bench] cpu baseline: oracle {L}^3, 1 step, {threads} threads")
+    orc = oracle.Sim(L, 20120221, nthreads=threads, **wl)
+    t0 = time.perf_counter()
+    orc.step(1)
+    dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(L ** 3 / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 step of the {L}^3 lattice ({L ** 3} site updates, {dt:.1f} s)",
+            "cpu": model}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * lbfss — fluctuating non-ideal lattice Boltzmann (D3Q19) on AMD Instinct
+ * MI355X (gfx950).  C ABI: plain pointers and sizes, no C++ or framework types.
+ *
+ * The model is the Langevin lattice-Boltzmann method of Gross & Varnik,
+ * "Simulation of static critical phenomena in non-ideal fluids with the
+ * Lattice Boltzmann method", Sec. III A (Eqs. (lbe), (mom), (lbnoise)), with
+ * the Ginzburg-Landau free energy of Sec. II A (Eqs. (fef), (landau-pot)),
+ * on a periodic three-dimensional D3Q19 lattice.  One time step:
+ *   1. rho = sum_i f_i, j = sum_i c_i f_i                         (Eq. (mom))
+ *   2. mu  = a (rho - rho_c) + b (rho - rho_c)^3 - kappa lap(rho) (Sec. II A)
+ *   3. F   = -rho grad(mu) + c_s^2 grad(rho)   (the non-ideal pressure as a
+ *            force, div P = rho grad(dF/dphi), with the ideal lattice-gas
+ *            pressure cancelled; c_s^2 = 1/3)
+ *   4. moment-space BGK collision with Guo forcing, u = (j + F/2)/rho, one
+ *      relaxation time tau for every non-conserved moment    (Eq. (lbe))
+ *   5. Gaussian noise on the 15 non-conserved moments a with variance
+ *      rho kT (1/tau)(2 - 1/tau) N_a / c_s^2   (Eq. (lbnoise) at c_s^2 = 1/3);
+ *      the normals come from Philox4x32-10 (Salmon et al., SC'11) with key
+ *      (seed_lo, seed_hi) and counter (site, step_lo, call, step_hi), call
+ *      0..3, through Box-Muller on pairs of uniforms ((w >> 9) + 1/2) 2^-23
+ *   6. streaming f_i(r + c_i, t + 1) = f*_i(r, t)
+ * Observables of the finite-size-scaling analysis are accumulated on sample
+ * steps: block order-parameter moments (Sec. II B, Eqs. (mL), (ML), (chiL),
+ * (chiL-lowT), (CL)) and the structure factor along the lattice axes
+ * (Sec. IV A, Eq. (G-comput)), with phi = (rho - rho0)/rho0 and rho0 the
+ * global mean density (Sec. II A, Eq. (op)).
+ *
+ * Lattice layout seen through this interface: site = x + L*(y + L*z);
+ * populations are [19][L^3] in the velocity order
+ *   0 (0,0,0); 1 (1,0,0) 2 (-1,0,0) 3 (0,1,0) 4 (0,-1,0) 5 (0,0,1) 6 (0,0,-1);
+ *   7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0) 11 (1,0,1) 12 (-1,0,-1)
+ *   13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1) 16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1)
+ * with weights 1/3, 1/18 (axis), 1/36 (diagonal).  The populations passed
+ * in and out are the post-streaming f_i(r, t) of the current step t.
+ *
+ * Errors: every int-returning call returns LB_OK (0) or a negative LB_E*
+ * code; lb_strerror names it.  LB_EUNSTABLE is sticky: once a kernel has
+ * met rho <= 0 or a non-finite value (the positivity condition of Sec. III B,
+ * Eq. (den_fluct_constr)), every later synchronising call returns it.
+ *
+ * Threads: a handle must not be used from two threads at once.  Handles are
+ * independent of each other.
+ * Streams: all device work of a handle is ordered on one HIP stream (its own
+ * unless lb_set_stream gives another).  lb_step is asynchronous; lb_sync,
+ * lb_moments, lb_fields and lb_set_populations synchronise that stream.
+ * Determinism: results depend only on (L, parameters, seed, step count) of
+ * each replica, never on the batch it runs in, the launch plan or the stream.
+ */
+#ifndef LBFSS_H
+#define LBFSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,    /* an argument is out of range or inconsistent */
+    LB_ENOMEM = -2,    /* a device or host allocation failed */
+    LB_EDEVICE = -3,   /* a HIP runtime call failed (no device, launch error) */
+    LB_EUNSTABLE = -4, /* sticky: rho <= 0 or a non-finite value was met */
+    LB_ESTATE = -5     /* the call is not valid in the handle's current state */
+};
+
+/* storage of the populations in device memory (compute is always FP32):
+ * the deviation (f_i - w_i rho_c) / w_i in IEEE binary32 or binary16 */
+enum { LB_FP32 = 0, LB_FP16 = 1 };
+
+/* lb_params.flags */
+enum { LB_FORCE_OFF = 1 /* F = 0: the ideal lattice gas (a test of the noise) */ };
+
+#define LB_MAX_LEVELS 16
+
+typedef struct {
+    double a;          /* r of Eq. (landau-pot): coefficient of (rho - rho_c) in mu */
+    double b;          /* u of Eq. (landau-pot): coefficient of (rho - rho_c)^3, >= 0 */
+    double kappa;      /* square-gradient coefficient of Eq. (fef), >= 0 */
+    double rho_c;      /* reference density rho_c > 0 of the Landau potential */
+    double kT;         /* noise temperature k_B T >= 0 of Eq. (lbnoise) */
+    double tau;        /* relaxation time, > 1/2 */
+    double init_sigma; /* standard deviation of the initial density, >= 0 */
+    int32_t storage;   /* LB_FP32 or LB_FP16 */
+    int32_t sample_every; /* > 0: sample after every such step; 0: never */
+    int32_t n_levels;  /* block edges L_b = L / 2^l, l = 1..n_levels while integer; 0 = all */
+    int32_t flags;     /* LB_FORCE_OFF or 0 */
+    int32_t series_capacity; /* per-sample records kept (ring buffer); 0 = none */
+    int32_t reserved;  /* must be 0 */
+} lb_params;
+
+typedef struct {
+    int32_t Lb;        /* box edge */
+    int32_t reserved;
+    int64_t n_boxes;   /* boxes per sample, (L / Lb)^3 */
+    /* sums over all boxes of all samples of m, m^2, m^3, m^4, |m|, E, E^2 with
+     * m = Lb^-3 sum_box phi (Eq. (mL)) and E = (2 Lb^3)^-1 sum_box phi^2 */
+    double sum_m, sum_m2, sum_m3, sum_m4, sum_abs_m, sum_E, sum_E2;
+} lb_level_sums;
+
+typedef struct {
+    int64_t step;        /* steps taken so far (the step counter of the noise) */
+    int64_t n_samples;   /* samples accumulated since creation or lb_reset_moments */
+    double mass;         /* sum of rho over the lattice now (FP64 reduction) */
+    double momentum[3];  /* sum of j over the lattice now */
+    int32_t L;           /* lattice edge of the replica */
+    int32_t n_levels;    /* entries used in level[] */
+    int32_t n_k;         /* axis modes per axis, L/2 - 1 */
+    int32_t series_len;  /* records held in the ring, min(n_samples, capacity) */
+    int32_t series_record; /* doubles per record, 5 + 7 n_levels */
+    int32_t reserved;
+    lb_level_sums level[LB_MAX_LEVELS]; /* coarsest (L/2) first */
+} lb_moments_t;
+
+typedef struct {
+    int32_t n_replicas;
+    int32_t storage;
+    int64_t total_sites;   /* sum of L^3 over replicas */
+    int64_t device_bytes;  /* device memory held by the handle */
+    int64_t step;
+    int32_t kernel;        /* plan in use: LB_KERNEL_* */
+    int32_t tile_x, tile_y, tile_z; /* tile of the fused kernel */
+    int32_t graph_steps;   /* steps captured per graph replay, 0 = direct launches */
+    int32_t device;        /* HIP device ordinal */
+} lb_info_t;
+
+/* launch plans (results do not depend on the plan) */
+enum {
+    LB_KERNEL_SPLIT = 0, /* density pass, chemical-potential pass, collide pass */
+    LB_KERNEL_FUSED = 1  /* one z-marching pass with the density halo in LDS */
+};
+
+typedef struct {
+    int32_t kernel;      /* LB_KERNEL_SPLIT or LB_KERNEL_FUSED */
+    int32_t tile_x;      /* fused: tile edge along x (sites), <= L is clamped */
+    int32_t tile_y;      /* fused: tile edge along y */
+    int32_t tile_z;      /* fused: planes marched by one workgroup */
+    int32_t graph_steps; /* > 0: capture this many steps (rounded up to even) in a
+                          * HIP graph and replay it; 0: launch kernels directly */
+    int32_t reserved;
+} lb_plan;
+
+typedef struct lb_sim lb_sim; /* opaque, owned by the library */
+
+/* One periodic L^3 lattice (L >= 4).  Initial state: rho = rho_c +
+ * init_sigma g with g the first Box-Muller normal of Philox call
+ * (site, 0, 1 << 16, 0), u = 0, f_i = w_i rho.  *out receives the handle.
+ * Errors: LB_EINVAL for L < 4, L > 1024, tau <= 1/2, kT < 0, kappa < 0,
+ * b < 0, rho_c <= 0, init_sigma < 0, bad storage, flags, sample_every < 0,
+ * n_levels < 0 or series_capacity < 0; LB_ENOMEM; LB_EDEVICE. */
+int lb_create(int L, const lb_params *p, uint64_t seed, lb_sim **out);
+
+/* n >= 1 replicas advanced together, replica r of edge L[r], parameters
+ * p[r] and seed seeds[r].  All replicas must share storage and sample_every.
+ * Each replica evolves exactly as it would alone under lb_create. */
+int lb_create_batch(int n, const int *L, const lb_params *p, const uint64_t *seeds, lb_sim **out);
+
+/* Advance every replica by n >= 0 steps (asynchronous on the handle's stream). */
+int lb_step(lb_sim *s, int64_t n);
+
+/* Wait for the handle's work; LB_EUNSTABLE if the sticky flag is set. */
+int lb_sync(lb_sim *s);
+
+/* Accumulated observables of one replica (synchronising).  sk, if not NULL,
+ * receives 3 * n_k doubles: sk[a * n_k + m - 1] = sum over samples of
+ * L^-3 |sum_r phi e^{-i k_m r_a}|^2, k_m = 2 pi m / L, axis a = x, y, z.
+ * series, if not NULL, receives series_len records (oldest first) of
+ * series_record doubles: step, mass, momentum x, y, z, then per level
+ * (coarsest first) the box means of m, m^2, m^3, m^4, |m|, E, E^2. */
+int lb_moments(lb_sim *s, int replica, lb_moments_t *out, double *sk, double *series);
+
+/* Current fields of one replica copied to host memory owned by the caller
+ * (synchronising); any pointer may be NULL.  rho: L^3 doubles, j: 3 L^3
+ * ([3][L^3]), f: 19 L^3 ([19][L^3]) post-streaming populations. */
+int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f);
+
+/* Replace the populations of one replica by f ([19][L^3] doubles, post-
+ * streaming, host memory), rounded to the storage precision.  The step
+ * counter and accumulators are kept (synchronising). */
+int lb_set_populations(lb_sim *s, int replica, const double *f);
+
+/* Zero every replica's accumulators, sample count and series. */
+int lb_reset_moments(lb_sim *s);
+
+/* Order all later device work of the handle on hip_stream (a hipStream_t;
+ * NULL selects the handle's own stream).  Synchronises the previous stream. */
+int lb_set_stream(lb_sim *s, void *hip_stream);
+
+/* Device allocator used by handles created afterwards (process-wide).
+ * alloc(bytes, ctx) returns device memory or NULL; free_(ptr, ctx) releases
+ * it.  NULL functions restore hipMalloc / hipFree. */
+int lb_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void *), void *ctx);
+
+/* Launch plan; LB_EINVAL for unknown kernels or tiles. */
+int lb_set_plan(lb_sim *s, const lb_plan *plan);
+int lb_get_plan(lb_sim *s, lb_plan *plan);
+
+/* Autotuner: time each candidate plan over `steps` steps (the steps are
+ * taken: the state advances by steps * candidates), keep the fastest and
+ * report it in *best (may be NULL).  Results are plan-independent. */
+int lb_tune(lb_sim *s, int steps, lb_plan *best);
+
+int lb_info(lb_sim *s, lb_info_t *out);
+
+/* Release every resource of the handle (NULL is ignored). */
+void lb_destroy(lb_sim *s);
+
+/* Static description of an error code. */
+const char *lb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBFSS_H */

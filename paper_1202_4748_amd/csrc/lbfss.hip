@@ -1,0 +1,763 @@
+// Host runtime of the lbfss C ABI (include/lbfss.h): device memory, replica
+// tables, the step loop (direct launches or replayed HIP graphs), the
+// sample-step pipeline, field import/export and the launch-plan autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbfss.h"
+#include "lbfss_fused.hpp"
+#include "lbfss_sample.hpp"
+
+using namespace lbfss;
+
+namespace {
+
+struct Allocator {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*free_)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+Allocator g_alloc;
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+struct lb_sim {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    Allocator alloc;
+    std::vector<void *> blocks;
+    int64_t device_bytes = 0;
+
+    int storage = LB_FP32;
+    int nrep = 0;
+    std::vector<int> L;
+    std::vector<lb_params> P;
+    std::vector<uint64_t> seeds;
+    std::vector<RepDesc> hdesc;
+    int64_t total_sites = 0;
+    int max_L = 0;
+
+    RepDesc *d_desc = nullptr;
+    float *d_sigma0 = nullptr;
+    void *pop[2] = {nullptr, nullptr};
+    float *d_drho = nullptr;
+    float *d_mu = nullptr;
+    uint64_t *d_step = nullptr;
+    int *d_err = nullptr;
+
+    // sampling
+    int sample_every = 0;
+    std::vector<SampDesc> hsd;
+    SampDesc *d_sd = nullptr;
+    int64_t *d_cum_rows = nullptr, *d_cum_cols = nullptr, *d_cum_bx = nullptr, *d_cum_by = nullptr,
+            *d_cum_bz = nullptr;
+    int64_t n_rows = 0, n_cols = 0, n_bx = 0, n_by = 0, n_bz = 0;
+    std::vector<int64_t *> d_cum_coarse;
+    std::vector<int64_t> n_coarse;
+    int max_nlev = 0;
+    BoxChunk *d_chunks = nullptr;
+    int n_chunks = 0;
+    double *d_parts = nullptr;
+    float *d_snap = nullptr;
+    double *d_ws = nullptr;
+    double *d_acc = nullptr;
+    double *d_series = nullptr;
+    int64_t *d_nsamp = nullptr;
+    int64_t acc_len = 0, series_len = 0;
+
+    // fused plan work table
+    FusedTile *d_tiles = nullptr;
+    int n_tiles = 0;
+    int tiles_for[3] = {0, 0, 0};
+
+    int64_t t = 0;
+    lb_plan plan{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0};
+    hipGraphExec_t gexec = nullptr;
+    int g_steps = 0;
+};
+
+namespace {
+
+int hip_fail(hipError_t e) { return e == hipSuccess ? LB_OK : (e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE); }
+
+#define HIPCHK(x)                                 \
+    do {                                          \
+        hipError_t e_ = (x);                      \
+        if (e_ != hipSuccess) return hip_fail(e_); \
+    } while (0)
+
+void *dev_alloc(lb_sim *s, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (s->alloc.alloc) {
+        p = s->alloc.alloc(bytes, s->alloc.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) {
+        s->blocks.push_back(p);
+        s->device_bytes += (int64_t)bytes;
+    }
+    return p;
+}
+
+void dev_free_all(lb_sim *s) {
+    for (void *p : s->blocks) {
+        if (s->alloc.free_) s->alloc.free_(p, s->alloc.ctx);
+        else (void)hipFree(p);
+    }
+    s->blocks.clear();
+}
+
+template <typename T>
+int upload(lb_sim *s, T **dst, const std::vector<T> &src) {
+    *dst = (T *)dev_alloc(s, sizeof(T) * std::max<size_t>(src.size(), 1));
+    if (!*dst) return LB_ENOMEM;
+    if (!src.empty())
+        HIPCHK(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s->stream));
+    return LB_OK;
+}
+
+int64_t rounds_up_even(int64_t v) { return (v + 1) & ~int64_t(1); }
+
+std::vector<int> block_levels(int L, int n_levels) {
+    std::vector<int> out;
+    int Lb = L;
+    while (Lb % 2 == 0 && Lb / 2 >= 1) {
+        Lb /= 2;
+        out.push_back(Lb);
+        if (n_levels > 0 && (int)out.size() == n_levels) break;
+        if ((int)out.size() == kMaxLevels) break;
+    }
+    return out;
+}
+
+int check_params(int L, const lb_params *p) {
+    if (!p) return LB_EINVAL;
+    if (L < 4 || L > 1024) return LB_EINVAL;
+    if (!(p->tau > 0.5) || !(p->kT >= 0) || !(p->kappa >= 0) || !(p->b >= 0) || !(p->rho_c > 0) ||
+        !(p->init_sigma >= 0) || !std::isfinite(p->a))
+        return LB_EINVAL;
+    if (p->storage != LB_FP32 && p->storage != LB_FP16) return LB_EINVAL;
+    if ((p->flags & ~LB_FORCE_OFF) != 0) return LB_EINVAL;
+    if (p->sample_every < 0 || p->n_levels < 0 || p->series_capacity < 0 || p->reserved != 0) return LB_EINVAL;
+    return LB_OK;
+}
+
+template <typename T>
+void launch_step(lb_sim *s, int cur, int koff) {
+    const T *in = (const T *)s->pop[cur];
+    T *out = (T *)s->pop[cur ^ 1];
+    if (s->plan.kernel == LB_KERNEL_FUSED && s->n_tiles > 0) {
+        launch_fused<T>(s->d_desc, s->d_tiles, s->n_tiles, in, out, s->d_step, koff, s->d_err,
+                        s->plan.tile_x, s->plan.tile_y, s->stream);
+        return;
+    }
+    const int64_t nb = ceil_div(s->total_sites, kBlock);
+    hipLaunchKernelGGL(k_density<T>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
+                       s->total_sites, in, s->d_drho);
+    hipLaunchKernelGGL(k_chem_potential, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
+                       s->total_sites, (const float *)s->d_drho, s->d_mu);
+    hipLaunchKernelGGL(k_collide<T>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
+                       s->total_sites, in, out, (const float *)s->d_drho, (const float *)s->d_mu,
+                       (const uint64_t *)s->d_step, koff, s->d_err);
+}
+
+void enqueue_step(lb_sim *s, int cur, int koff) {
+    if (s->storage == LB_FP16) launch_step<__half>(s, cur, koff);
+    else launch_step<float>(s, cur, koff);
+}
+
+// Reduction stages shared by sampling and by lb_moments' current totals.
+template <typename T>
+void launch_totals(lb_sim *s, int cur) {
+    const int64_t nb = ceil_div(s->total_sites, kBlock);
+    hipLaunchKernelGGL(k_snapshot<T>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
+                       s->total_sites, (const T *)s->pop[cur], s->d_snap);
+    hipLaunchKernelGGL(k_rows, dim3((unsigned)ceil_div(s->n_rows, kBlock / 64)), dim3(kBlock), 0, s->stream,
+                       s->d_sd, s->d_cum_rows, s->nrep, s->total_sites, (const float *)s->d_snap, s->d_ws);
+    hipLaunchKernelGGL(k_cols, dim3((unsigned)ceil_div(s->n_cols, kBlock)), dim3(kBlock), 0, s->stream,
+                       s->d_sd, s->d_cum_cols, s->nrep, (const float *)s->d_snap, s->d_ws);
+    hipLaunchKernelGGL(k_globals, dim3(s->nrep), dim3(kBlock), 0, s->stream, s->d_sd, s->d_desc, s->d_ws);
+}
+
+void enqueue_totals(lb_sim *s, int cur) {
+    if (s->storage == LB_FP16) launch_totals<__half>(s, cur);
+    else launch_totals<float>(s, cur);
+}
+
+void enqueue_sample(lb_sim *s, int cur, int koff) {
+    enqueue_totals(s, cur);
+    hipLaunchKernelGGL(k_box_x, dim3((unsigned)ceil_div(s->n_bx, kBlock)), dim3(kBlock), 0, s->stream, s->d_sd,
+                       s->d_cum_bx, s->nrep, (const float *)s->d_snap, s->d_ws);
+    hipLaunchKernelGGL(k_box_y, dim3((unsigned)ceil_div(s->n_by, kBlock)), dim3(kBlock), 0, s->stream, s->d_sd,
+                       s->d_cum_by, s->nrep, s->d_ws);
+    hipLaunchKernelGGL(k_box_z, dim3((unsigned)ceil_div(s->n_bz, kBlock)), dim3(kBlock), 0, s->stream, s->d_sd,
+                       s->d_cum_bz, s->nrep, s->d_ws);
+    for (int lev = s->max_nlev - 2; lev >= 0; --lev) {
+        if (s->n_coarse[lev] == 0) continue;
+        hipLaunchKernelGGL(k_coarsen, dim3((unsigned)ceil_div(s->n_coarse[lev], kBlock)), dim3(kBlock), 0,
+                           s->stream, s->d_sd, s->d_cum_coarse[lev], s->nrep, lev, s->d_ws);
+    }
+    hipLaunchKernelGGL(k_level_partials, dim3(s->n_chunks), dim3(kBlock), 0, s->stream, s->d_sd, s->d_chunks,
+                       s->d_ws, s->d_parts);
+    hipLaunchKernelGGL(k_finalize, dim3(s->nrep), dim3(kBlock), 0, s->stream, s->d_sd, s->d_ws,
+                       (const double *)s->d_parts, s->d_acc, s->d_series, s->d_nsamp, (const uint64_t *)s->d_step,
+                       koff);
+}
+
+bool sampling(const lb_sim *s) { return s->sample_every > 0; }
+
+int64_t graph_period(const lb_sim *s) {
+    int64_t P = 2;
+    if (sampling(s)) {
+        const int64_t e = s->sample_every;
+        P = (e % 2 == 0) ? e : 2 * e;
+    }
+    return P;
+}
+
+void drop_graph(lb_sim *s) {
+    if (s->gexec) {
+        (void)hipGraphExecDestroy(s->gexec);
+        s->gexec = nullptr;
+    }
+    s->g_steps = 0;
+}
+
+// Capture G steps (G a multiple of the graph period) starting from an even
+// step count whose value is a multiple of the period.
+int build_graph(lb_sim *s, int G) {
+    drop_graph(s);
+    hipStream_t keep = s->stream;
+    s->stream = s->cap_stream;
+    HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < G; ++k) {
+        enqueue_step(s, k & 1, k);
+        if (sampling(s) && (k + 1) % s->sample_every == 0) enqueue_sample(s, (k + 1) & 1, k + 1);
+    }
+    hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s->cap_stream, s->d_step, (int64_t)G);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
+    s->stream = keep;
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipGraphInstantiate(&s->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        s->gexec = nullptr;
+        return hip_fail(e);
+    }
+    s->g_steps = G;
+    return LB_OK;
+}
+
+int build_sampling(lb_sim *s) {
+    int64_t ws_len = 0, acc_len = 0, ser_len = 0, parts_rows = 0;
+    std::vector<BoxChunk> chunks;
+    std::vector<int64_t> cum_rows{0}, cum_cols{0}, cum_bx{0}, cum_by{0}, cum_bz{0};
+    s->max_nlev = 0;
+    for (int r = 0; r < s->nrep; ++r)
+        s->max_nlev = std::max<int>(s->max_nlev, (int)block_levels(s->L[r], s->P[r].n_levels).size());
+    std::vector<std::vector<int64_t>> cum_coarse(std::max(s->max_nlev - 1, 0), std::vector<int64_t>{0});
+    for (int r = 0; r < s->nrep; ++r) {
+        const int L = s->L[r];
+        SampDesc d;
+        std::memset(&d, 0, sizeof(d));
+        std::vector<int> lev = block_levels(L, s->P[r].n_levels);
+        d.L = L;
+        d.nlev = (int)lev.size();
+        d.Lmin = lev.empty() ? L : lev.back();
+        d.nb = L / d.Lmin;
+        d.n_k = L / 2 - 1;
+        d.series_cap = s->P[r].series_capacity;
+        d.rec_len = 5 + kMoments * d.nlev;
+        d.site_off = s->hdesc[r].site_off;
+        const int64_t LL = (int64_t)L * L;
+        d.rows_off = ws_len; ws_len += 4 * LL;
+        d.cols_off = ws_len; ws_len += LL;
+        d.planes_off = ws_len; ws_len += 3 * L;
+        d.a_off = ws_len; ws_len += 2 * LL * d.nb;
+        d.b_off = ws_len; ws_len += 2 * (int64_t)L * d.nb * d.nb;
+        for (int l = 0; l < d.nlev; ++l) {
+            const int64_t nbl = L / lev[l];
+            d.lev_L[l] = lev[l];
+            d.lev_off[l] = ws_len;
+            ws_len += 2 * nbl * nbl * nbl;
+            d.chunk_first[l] = (int64_t)chunks.size();
+            const int64_t nboxes = nbl * nbl * nbl;
+            int cnt = 0;
+            for (int64_t f = 0; f < nboxes; f += kChunkBoxes, ++cnt)
+                chunks.push_back(BoxChunk{r, l, f, (int32_t)std::min<int64_t>(kChunkBoxes, nboxes - f), 0});
+            d.chunk_count[l] = cnt;
+        }
+        d.glob_off = ws_len; ws_len += 8;
+        d.acc_off = acc_len; acc_len += (int64_t)kMoments * d.nlev + 3 * d.n_k;
+        d.series_off = ser_len; ser_len += (int64_t)d.series_cap * d.rec_len;
+        cum_rows.push_back(cum_rows.back() + LL);
+        cum_cols.push_back(cum_cols.back() + LL);
+        cum_bx.push_back(cum_bx.back() + LL * d.nb);
+        cum_by.push_back(cum_by.back() + (int64_t)L * d.nb * d.nb);
+        cum_bz.push_back(cum_bz.back() + (int64_t)d.nb * d.nb * d.nb);
+        for (int l = 0; l + 1 < s->max_nlev; ++l) {
+            int64_t n = 0;
+            if (l + 1 < d.nlev) {
+                const int64_t nbl = L / lev[l];
+                n = nbl * nbl * nbl;
+            }
+            cum_coarse[l].push_back(cum_coarse[l].back() + n);
+        }
+        s->hsd.push_back(d);
+    }
+    parts_rows = (int64_t)chunks.size();
+    s->n_rows = cum_rows.back();
+    s->n_cols = cum_cols.back();
+    s->n_bx = cum_bx.back();
+    s->n_by = cum_by.back();
+    s->n_bz = cum_bz.back();
+    int rc;
+    if ((rc = upload(s, &s->d_sd, s->hsd))) return rc;
+    if ((rc = upload(s, &s->d_cum_rows, cum_rows))) return rc;
+    if ((rc = upload(s, &s->d_cum_cols, cum_cols))) return rc;
+    if ((rc = upload(s, &s->d_cum_bx, cum_bx))) return rc;
+    if ((rc = upload(s, &s->d_cum_by, cum_by))) return rc;
+    if ((rc = upload(s, &s->d_cum_bz, cum_bz))) return rc;
+    s->d_cum_coarse.assign(cum_coarse.size(), nullptr);
+    s->n_coarse.assign(cum_coarse.size(), 0);
+    for (size_t l = 0; l < cum_coarse.size(); ++l) {
+        if ((rc = upload(s, &s->d_cum_coarse[l], cum_coarse[l]))) return rc;
+        s->n_coarse[l] = cum_coarse[l].back();
+    }
+    if ((rc = upload(s, &s->d_chunks, chunks))) return rc;
+    s->n_chunks = (int)chunks.size();
+    s->d_parts = (double *)dev_alloc(s, sizeof(double) * kMoments * std::max<int64_t>(parts_rows, 1));
+    s->d_snap = (float *)dev_alloc(s, sizeof(float) * 4 * s->total_sites);
+    s->d_ws = (double *)dev_alloc(s, sizeof(double) * ws_len);
+    s->d_acc = (double *)dev_alloc(s, sizeof(double) * std::max<int64_t>(acc_len, 1));
+    s->d_series = (double *)dev_alloc(s, sizeof(double) * std::max<int64_t>(ser_len, 1));
+    s->d_nsamp = (int64_t *)dev_alloc(s, sizeof(int64_t) * s->nrep);
+    if (!s->d_parts || !s->d_snap || !s->d_ws || !s->d_acc || !s->d_series || !s->d_nsamp) return LB_ENOMEM;
+    s->acc_len = acc_len;
+    s->series_len = ser_len;
+    HIPCHK(hipMemsetAsync(s->d_acc, 0, sizeof(double) * std::max<int64_t>(acc_len, 1), s->stream));
+    HIPCHK(hipMemsetAsync(s->d_series, 0, sizeof(double) * std::max<int64_t>(ser_len, 1), s->stream));
+    HIPCHK(hipMemsetAsync(s->d_nsamp, 0, sizeof(int64_t) * s->nrep, s->stream));
+    return LB_OK;
+}
+
+int build_tiles(lb_sim *s, int tx, int ty, int tz) {
+    std::vector<FusedTile> tiles;
+    if (make_fused_tiles(s->hdesc, tx, ty, tz, tiles) != 0) return LB_EINVAL;
+    if (s->d_tiles && s->tiles_for[0] == tx && s->tiles_for[1] == ty && s->tiles_for[2] == tz) return LB_OK;
+    int rc = upload(s, &s->d_tiles, tiles);
+    if (rc) return rc;
+    s->n_tiles = (int)tiles.size();
+    s->tiles_for[0] = tx;
+    s->tiles_for[1] = ty;
+    s->tiles_for[2] = tz;
+    return LB_OK;
+}
+
+int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, lb_sim **out) {
+    if (!out || n < 1 || !L || !p || !seeds) return LB_EINVAL;
+    *out = nullptr;
+    for (int r = 0; r < n; ++r) {
+        int rc = check_params(L[r], &p[r]);
+        if (rc) return rc;
+        if (p[r].storage != p[0].storage || p[r].sample_every != p[0].sample_every) return LB_EINVAL;
+    }
+    lb_sim *s = new (std::nothrow) lb_sim();
+    if (!s) return LB_ENOMEM;
+    s->alloc = g_alloc;
+    int rc = LB_OK;
+    auto fail = [&](int code) {
+        lb_destroy(s);
+        return code;
+    };
+    if (hipGetDevice(&s->device) != hipSuccess) return fail(LB_EDEVICE);
+    if (hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking) != hipSuccess) return fail(LB_EDEVICE);
+    if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(LB_EDEVICE);
+    s->stream = s->own_stream;
+    s->nrep = n;
+    s->storage = p[0].storage;
+    s->sample_every = p[0].sample_every;
+    std::vector<float> sigma0;
+    for (int r = 0; r < n; ++r) {
+        s->L.push_back(L[r]);
+        s->P.push_back(p[r]);
+        s->seeds.push_back(seeds[r]);
+        RepDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.L = L[r];
+        d.flags = p[r].flags;
+        d.N = (int64_t)L[r] * L[r] * L[r];
+        d.site_off = s->total_sites;
+        d.a = (float)p[r].a;
+        d.b = (float)p[r].b;
+        d.kappa = (float)p[r].kappa;
+        d.rho_c = (float)p[r].rho_c;
+        const double gam = 1.0 - 1.0 / p[r].tau;
+        d.gamma = (float)gam;
+        d.half1pg = (float)(0.5 * (1.0 + gam));
+        d.noise_amp = (float)std::sqrt(3.0 * p[r].kT * (1.0 - gam * gam));
+        d.key0 = (uint32_t)seeds[r];
+        d.key1 = (uint32_t)(seeds[r] >> 32);
+        s->hdesc.push_back(d);
+        sigma0.push_back((float)p[r].init_sigma);
+        s->total_sites += d.N;
+        s->max_L = std::max(s->max_L, L[r]);
+    }
+    const size_t esz = s->storage == LB_FP16 ? 2 : 4;
+    for (int b = 0; b < 2; ++b) {
+        s->pop[b] = dev_alloc(s, esz * Q * (size_t)s->total_sites);
+        if (!s->pop[b]) return fail(LB_ENOMEM);
+    }
+    s->d_drho = (float *)dev_alloc(s, sizeof(float) * s->total_sites);
+    s->d_mu = (float *)dev_alloc(s, sizeof(float) * s->total_sites);
+    s->d_step = (uint64_t *)dev_alloc(s, sizeof(uint64_t));
+    s->d_err = (int *)dev_alloc(s, sizeof(int));
+    if (!s->d_drho || !s->d_mu || !s->d_step || !s->d_err) return fail(LB_ENOMEM);
+    if ((rc = upload(s, &s->d_desc, s->hdesc))) return fail(rc);
+    if ((rc = upload(s, &s->d_sigma0, sigma0))) return fail(rc);
+    if (hipMemsetAsync(s->d_step, 0, sizeof(uint64_t), s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    if (hipMemsetAsync(s->d_err, 0, sizeof(int), s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    const int64_t nb = ceil_div(s->total_sites, kBlock);
+    hipLaunchKernelGGL(k_init_density, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc,
+                       (const float *)s->d_sigma0, s->nrep, s->total_sites, s->d_drho);
+    if (s->storage == LB_FP16)
+        hipLaunchKernelGGL(k_init_populations<__half>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc,
+                           s->nrep, s->total_sites, (const float *)s->d_drho, (__half *)s->pop[0]);
+    else
+        hipLaunchKernelGGL(k_init_populations<float>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc,
+                           s->nrep, s->total_sites, (const float *)s->d_drho, (float *)s->pop[0]);
+    if (hipGetLastError() != hipSuccess) return fail(LB_EDEVICE);
+    if ((rc = build_sampling(s))) return fail(rc);
+    // default plan: the fused kernel when every replica supports its tiles
+    lb_plan def{LB_KERNEL_FUSED, 64, 8, 16, 0, 0};
+    default_fused_tile(s->hdesc, def.tile_x, def.tile_y, def.tile_z);
+    if (lb_set_plan(s, &def) != LB_OK) {
+        lb_plan split{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0};
+        if ((rc = lb_set_plan(s, &split))) return fail(rc);
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    *out = s;
+    return LB_OK;
+}
+
+int check_err(lb_sim *s) {
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, s->d_err, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return h ? LB_EUNSTABLE : LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_create(int L, const lb_params *p, uint64_t seed, lb_sim **out) {
+    return create_impl(1, &L, p, &seed, out);
+}
+
+int lb_create_batch(int n, const int *L, const lb_params *p, const uint64_t *seeds, lb_sim **out) {
+    return create_impl(n, L, p, seeds, out);
+}
+
+int lb_step(lb_sim *s, int64_t n) {
+    if (!s || n < 0) return LB_EINVAL;
+    const int64_t P = graph_period(s);
+    while (n > 0) {
+        const int G = s->plan.graph_steps;
+        if (G > 0 && s->t % P == 0 && n >= G) {
+            if (!s->gexec || s->g_steps != G) {
+                int rc = build_graph(s, G);
+                if (rc) return rc;
+            }
+            HIPCHK(hipGraphLaunch(s->gexec, s->stream));
+            s->t += G;
+            n -= G;
+            continue;
+        }
+        const int cur = (int)(s->t & 1);
+        enqueue_step(s, cur, 0);
+        hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s->stream, s->d_step, (int64_t)1);
+        s->t += 1;
+        if (sampling(s) && s->t % s->sample_every == 0) enqueue_sample(s, cur ^ 1, 0);
+        n -= 1;
+    }
+    HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+int lb_sync(lb_sim *s) {
+    if (!s) return LB_EINVAL;
+    return check_err(s);
+}
+
+int lb_moments(lb_sim *s, int replica, lb_moments_t *out, double *sk, double *series) {
+    if (!s || !out || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    enqueue_totals(s, (int)(s->t & 1));
+    HIPCHK(hipGetLastError());
+    const SampDesc &d = s->hsd[replica];
+    std::vector<double> acc((size_t)kMoments * d.nlev + 3 * d.n_k);
+    double gl[8];
+    int64_t ns = 0;
+    HIPCHK(hipMemcpyAsync(acc.data(), s->d_acc + d.acc_off, sizeof(double) * acc.size(), hipMemcpyDeviceToHost,
+                          s->stream));
+    HIPCHK(hipMemcpyAsync(gl, s->d_ws + d.glob_off, sizeof(double) * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(&ns, s->d_nsamp + replica, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    std::memset(out, 0, sizeof(*out));
+    out->step = s->t;
+    out->n_samples = ns;
+    out->mass = gl[2];
+    out->momentum[0] = gl[3];
+    out->momentum[1] = gl[4];
+    out->momentum[2] = gl[5];
+    out->L = d.L;
+    out->n_levels = d.nlev;
+    out->n_k = d.n_k;
+    out->series_record = d.rec_len;
+    out->series_len = (int32_t)std::min<int64_t>(ns, d.series_cap);
+    for (int l = 0; l < d.nlev; ++l) {
+        lb_level_sums &ls = out->level[l];
+        const int64_t nbl = d.L / d.lev_L[l];
+        ls.Lb = d.lev_L[l];
+        ls.n_boxes = nbl * nbl * nbl;
+        const double *a = acc.data() + (size_t)l * kMoments;
+        ls.sum_m = a[0];
+        ls.sum_m2 = a[1];
+        ls.sum_m3 = a[2];
+        ls.sum_m4 = a[3];
+        ls.sum_abs_m = a[4];
+        ls.sum_E = a[5];
+        ls.sum_E2 = a[6];
+    }
+    if (sk) std::memcpy(sk, acc.data() + (size_t)kMoments * d.nlev, sizeof(double) * 3 * d.n_k);
+    if (series && out->series_len > 0) {
+        std::vector<double> ring((size_t)d.series_cap * d.rec_len);
+        HIPCHK(hipMemcpy(ring.data(), s->d_series + d.series_off, sizeof(double) * ring.size(),
+                         hipMemcpyDeviceToHost));
+        const int64_t first = ns > d.series_cap ? ns % d.series_cap : 0;
+        for (int64_t i = 0; i < out->series_len; ++i) {
+            const int64_t slot = (first + i) % d.series_cap;
+            std::memcpy(series + i * d.rec_len, ring.data() + slot * d.rec_len, sizeof(double) * d.rec_len);
+        }
+    }
+    return check_err(s);
+}
+
+int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f) {
+    if (!s || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    const RepDesc &d = s->hdesc[replica];
+    const size_t N = (size_t)d.N;
+    double *drho = rho ? (double *)dev_alloc(s, sizeof(double) * N) : nullptr;
+    double *dj = j ? (double *)dev_alloc(s, sizeof(double) * 3 * N) : nullptr;
+    double *df = f ? (double *)dev_alloc(s, sizeof(double) * Q * N) : nullptr;
+    int rc = LB_OK;
+    if ((rho && !drho) || (j && !dj) || (f && !df)) rc = LB_ENOMEM;
+    const int cur = (int)(s->t & 1);
+    if (rc == LB_OK) {
+        const unsigned nb = (unsigned)ceil_div(d.N, kBlock);
+        if (s->storage == LB_FP16)
+            hipLaunchKernelGGL(k_export<__half>, dim3(nb), dim3(kBlock), 0, s->stream, d,
+                               (const __half *)s->pop[cur] + Q * d.site_off, drho, dj, df);
+        else
+            hipLaunchKernelGGL(k_export<float>, dim3(nb), dim3(kBlock), 0, s->stream, d,
+                               (const float *)s->pop[cur] + Q * d.site_off, drho, dj, df);
+        if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
+    }
+    if (rc == LB_OK && rho && hipMemcpyAsync(rho, drho, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream))
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && j && hipMemcpyAsync(j, dj, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s->stream))
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && f && hipMemcpyAsync(f, df, sizeof(double) * Q * N, hipMemcpyDeviceToHost, s->stream))
+        rc = LB_EDEVICE;
+    if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
+    // release the temporaries (they are the most recent blocks)
+    for (void *p : {(void *)df, (void *)dj, (void *)drho}) {
+        if (!p) continue;
+        auto it = std::find(s->blocks.begin(), s->blocks.end(), p);
+        if (it != s->blocks.end()) s->blocks.erase(it);
+        if (s->alloc.free_) s->alloc.free_(p, s->alloc.ctx);
+        else (void)hipFree(p);
+    }
+    s->device_bytes -= (int64_t)((rho ? N : 0) + (j ? 3 * N : 0) + (f ? Q * N : 0)) * (int64_t)sizeof(double);
+    if (rc) return rc;
+    return check_err(s);
+}
+
+int lb_set_populations(lb_sim *s, int replica, const double *f) {
+    if (!s || !f || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    const RepDesc &d = s->hdesc[replica];
+    const size_t bytes = sizeof(double) * Q * (size_t)d.N;
+    double *df = (double *)dev_alloc(s, bytes);
+    if (!df) return LB_ENOMEM;
+    int rc = LB_OK;
+    const int cur = (int)(s->t & 1);
+    if (hipMemcpyAsync(df, f, bytes, hipMemcpyHostToDevice, s->stream) != hipSuccess) rc = LB_EDEVICE;
+    if (rc == LB_OK) {
+        const unsigned nb = (unsigned)ceil_div(d.N, kBlock);
+        if (s->storage == LB_FP16)
+            hipLaunchKernelGGL(k_import<__half>, dim3(nb), dim3(kBlock), 0, s->stream, d, (const double *)df,
+                               (__half *)s->pop[cur] + Q * d.site_off);
+        else
+            hipLaunchKernelGGL(k_import<float>, dim3(nb), dim3(kBlock), 0, s->stream, d, (const double *)df,
+                               (float *)s->pop[cur] + Q * d.site_off);
+        if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
+    auto it = std::find(s->blocks.begin(), s->blocks.end(), (void *)df);
+    if (it != s->blocks.end()) s->blocks.erase(it);
+    if (s->alloc.free_) s->alloc.free_(df, s->alloc.ctx);
+    else (void)hipFree(df);
+    s->device_bytes -= (int64_t)bytes;
+    if (rc) return rc;
+    return check_err(s);
+}
+
+int lb_reset_moments(lb_sim *s) {
+    if (!s) return LB_EINVAL;
+    HIPCHK(hipMemsetAsync(s->d_acc, 0, sizeof(double) * std::max<int64_t>(s->acc_len, 1), s->stream));
+    HIPCHK(hipMemsetAsync(s->d_series, 0, sizeof(double) * std::max<int64_t>(s->series_len, 1), s->stream));
+    HIPCHK(hipMemsetAsync(s->d_nsamp, 0, sizeof(int64_t) * s->nrep, s->stream));
+    return LB_OK;
+}
+
+int lb_set_stream(lb_sim *s, void *hip_stream) {
+    if (!s) return LB_EINVAL;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->stream = hip_stream ? (hipStream_t)hip_stream : s->own_stream;
+    return LB_OK;
+}
+
+int lb_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void *), void *ctx) {
+    if ((alloc == nullptr) != (free_ == nullptr)) return LB_EINVAL;
+    g_alloc.alloc = alloc;
+    g_alloc.free_ = free_;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return LB_OK;
+}
+
+int lb_set_plan(lb_sim *s, const lb_plan *plan) {
+    if (!s || !plan) return LB_EINVAL;
+    if (plan->graph_steps < 0 || plan->graph_steps > 100000) return LB_EINVAL;
+    lb_plan p = *plan;
+    if (p.graph_steps > 0) {
+        const int64_t P = graph_period(s);
+        p.graph_steps = (int)(ceil_div(p.graph_steps, P) * P);
+    }
+    if (p.kernel == LB_KERNEL_FUSED) {
+        int rc = build_tiles(s, p.tile_x, p.tile_y, p.tile_z);
+        if (rc) return rc;
+    } else if (p.kernel != LB_KERNEL_SPLIT) {
+        return LB_EINVAL;
+    }
+    if (p.kernel != s->plan.kernel || p.tile_x != s->plan.tile_x || p.tile_y != s->plan.tile_y ||
+        p.tile_z != s->plan.tile_z || p.graph_steps != s->plan.graph_steps)
+        drop_graph(s);
+    s->plan = p;
+    return LB_OK;
+}
+
+int lb_get_plan(lb_sim *s, lb_plan *plan) {
+    if (!s || !plan) return LB_EINVAL;
+    *plan = s->plan;
+    return LB_OK;
+}
+
+int lb_tune(lb_sim *s, int steps, lb_plan *best) {
+    if (!s || steps < 1) return LB_EINVAL;
+    std::vector<lb_plan> cands;
+    cands.push_back(lb_plan{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0});
+    for (const auto &t : fused_tile_candidates(s->hdesc)) cands.push_back(lb_plan{LB_KERNEL_FUSED, t[0], t[1], t[2], 0, 0});
+    const int64_t P = graph_period(s);
+    const int gsteps = (int)(ceil_div(std::max<int64_t>(steps, 8), P) * P);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    lb_plan keep = s->plan, win = keep;
+    float best_ms = 1e30f;
+    int rc = LB_OK;
+    for (lb_plan c : cands) {
+        for (int g = 0; g < 2 && rc == LB_OK; ++g) {
+            c.graph_steps = g ? gsteps : 0;
+            if (lb_set_plan(s, &c) != LB_OK) break;
+            // align to the graph period, warm up (and capture)
+            int64_t align = (P - s->t % P) % P;
+            if ((rc = lb_step(s, align + (g ? gsteps : 1)))) break;
+            if ((rc = hip_fail(hipEventRecord(e0, s->stream)))) break;
+            if ((rc = lb_step(s, g ? gsteps : steps))) break;
+            if ((rc = hip_fail(hipEventRecord(e1, s->stream)))) break;
+            if ((rc = hip_fail(hipEventSynchronize(e1)))) break;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= (float)(g ? gsteps : steps);
+            if (ms < best_ms) {
+                best_ms = ms;
+                win = s->plan;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        (void)lb_set_plan(s, &keep);
+        return rc;
+    }
+    rc = lb_set_plan(s, &win);
+    if (best) *best = s->plan;
+    if (rc) return rc;
+    return check_err(s);
+}
+
+int lb_info(lb_sim *s, lb_info_t *out) {
+    if (!s || !out) return LB_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->n_replicas = s->nrep;
+    out->storage = s->storage;
+    out->total_sites = s->total_sites;
+    out->device_bytes = s->device_bytes;
+    out->step = s->t;
+    out->kernel = s->plan.kernel;
+    out->tile_x = s->plan.tile_x;
+    out->tile_y = s->plan.tile_y;
+    out->tile_z = s->plan.tile_z;
+    out->graph_steps = s->plan.graph_steps;
+    out->device = s->device;
+    return LB_OK;
+}
+
+void lb_destroy(lb_sim *s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graph(s);
+    dev_free_all(s);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    delete s;
+}
+
+const char *lb_strerror(int code) {
+    switch (code) {
+    case LB_OK: return "success";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "out of memory";
+    case LB_EDEVICE: return "HIP device or launch error";
+    case LB_EUNSTABLE: return "unstable: density <= 0 or non-finite value met";
+    case LB_ESTATE: return "call not valid in the current state";
+    }
+    return "unknown error";
+}
+
+}  // extern "C"

@@ -1,0 +1,383 @@
+// Sample-step kernels: the observables of the finite-size-scaling analysis
+// (Gross & Varnik, Sec. II B, Eqs. (mL), (ML), (chiL), (chiL-lowT), (CL)) and
+// the structure factor along the lattice axes (Sec. IV A, Eq. (G-comput)),
+// with the order parameter phi = (rho - rho0)/rho0, rho0 the global mean
+// density (Sec. II A, Eq. (op)).
+//
+// All reductions are FP64 and run in a fixed order, so a replica's results
+// are bit-identical whatever batch it is part of.  Each launch covers every
+// replica of a handle: per-stage prefix arrays `cum` map a flattened item
+// index to (replica, local item).
+#pragma once
+
+#include "lbfss_step.hpp"
+
+namespace lbfss {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMoments = 7;  // m, m^2, m^3, m^4, |m|, E, E^2
+
+struct SampDesc {
+    int32_t L, Lmin, nlev, nb;   // nb = L / Lmin boxes per axis at the finest level
+    int32_t n_k, series_cap, rec_len, pad;
+    int64_t site_off;            // first site (snapshot index) of the replica
+    int64_t rows_off;            // 4 * L^2 doubles: row sums of drho, jx, jy, jz, [4][z][y]
+    int64_t cols_off;            // L^2 doubles: column sums of drho over y, [z][x]
+    int64_t planes_off;          // 3 * L doubles: plane sums P_x, P_y, P_z of drho
+    int64_t a_off;               // 2 * L * L * nb: [2][z][y][bx]
+    int64_t b_off;               // 2 * L * nb * nb: [2][z][by][bx]
+    int64_t lev_off[kMaxLevels]; // 2 * (L/Lb)^3 each: [2][bz][by][bx], level 0 = L/2
+    int32_t lev_L[kMaxLevels];   // box edge of each level
+    int64_t chunk_first[kMaxLevels]; // first partial-sum chunk of each level
+    int32_t chunk_count[kMaxLevels];
+    int64_t acc_off;             // accumulators: nlev * 7 level sums, then 3 * n_k S(k) sums
+    int64_t series_off;          // series_cap * rec_len doubles
+    int64_t glob_off;            // 6 doubles: dbar, rhobar, mass, px, py, pz of the last reduction
+};
+
+// A chunk of consecutive boxes of one (replica, level) reduced by one
+// workgroup into one partial-sum row.
+struct BoxChunk {
+    int32_t rep, lev;
+    int64_t first;
+    int32_t count, pad;
+};
+
+__device__ __forceinline__ int find_cum(const int64_t *__restrict__ cum, int nrep, int64_t g) {
+    int lo = 0, hi = nrep - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cum[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Deterministic FP64 sum over a 256-thread workgroup (fixed tree).
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double out = sh[0];
+    __syncthreads();
+    return out;
+}
+
+// 1. Snapshot of drho and j at every site (pulled populations), FP32.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_snapshot(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T *__restrict__ pop,
+           float *__restrict__ snap) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= total) return;
+    const int r = find_rep(desc, nrep, g);
+    const RepDesc &d = desc[r];
+    const Nbr n(g - d.site_off, d.L);
+    float f[Q];
+    pull(pop + Q * d.site_off, d.N, n, f);
+    float jx, jy, jz;
+    momentum_of(f, jx, jy, jz);
+    snap[g] = drho_of(f);
+    snap[total + g] = jx;
+    snap[2 * total + g] = jy;
+    snap[3 * total + g] = jz;
+}
+
+// 2. Row sums over x of drho, jx, jy, jz: one 64-lane wave per (z, y) row.
+__global__ void __launch_bounds__(kBlock)
+k_rows(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep, int64_t total_sites,
+       const float *__restrict__ snap, double *__restrict__ ws) {
+    const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= cum[nrep]) return;  // whole wave leaves together
+    const int r = find_cum(cum, nrep, row);
+    const SampDesc &s = sd[r];
+    const int64_t lr = row - cum[r];
+    const int L = s.L;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t base = s.site_off + lr * L;
+    for (int x = lane; x < L; x += 64)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += (double)snap[c * total_sites + base + x];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double v = acc[c];
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+        acc[c] = v;
+    }
+    if (lane == 0) {
+        const int64_t LL = (int64_t)L * L;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ws[s.rows_off + c * LL + lr] = acc[c];
+    }
+}
+
+// 3. Column sums over y of drho for every (z, x).
+__global__ void __launch_bounds__(kBlock)
+k_cols(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep,
+       const float *__restrict__ snap, double *__restrict__ ws) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= cum[nrep]) return;
+    const int r = find_cum(cum, nrep, g);
+    const SampDesc &s = sd[r];
+    const int64_t li = g - cum[r];
+    const int L = s.L;
+    const int64_t z = li / L, x = li - z * L;
+    double acc = 0.0;
+    for (int y = 0; y < L; ++y) acc += (double)snap[s.site_off + x + L * (y + L * z)];
+    ws[s.cols_off + li] = acc;
+}
+
+// 4. Per replica (one workgroup each): plane sums, total mass and momentum,
+// and the mean density deviation dbar that defines phi.
+__global__ void __launch_bounds__(kBlock)
+k_globals(const SampDesc *__restrict__ sd, const RepDesc *__restrict__ desc, double *__restrict__ ws) {
+    __shared__ double sh[kBlock];
+    const int r = blockIdx.x;
+    const SampDesc &s = sd[r];
+    const int L = s.L;
+    const int64_t LL = (int64_t)L * L;
+    const double *rows = ws + s.rows_off;
+    const double *cols = ws + s.cols_off;
+    double *planes = ws + s.planes_off;
+    for (int n = threadIdx.x; n < L; n += kBlock) {
+        double px = 0.0, py = 0.0, pz = 0.0;
+        for (int k = 0; k < L; ++k) {
+            px += cols[(int64_t)k * L + n];   // sum over z of column sums at x = n
+            py += rows[(int64_t)k * L + n];   // sum over z of row sums at y = n
+            pz += rows[(int64_t)n * L + k];   // sum over y of row sums at z = n
+        }
+        planes[n] = px;
+        planes[L + n] = py;
+        planes[2 * L + n] = pz;
+    }
+    // totals: each thread sums a fixed strided subset of rows, then a tree
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < LL; i += kBlock)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) t[c] += rows[c * LL + i];
+    double tot[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tot[c] = block_sum(t[c], sh);
+    if (threadIdx.x == 0) {
+        const double N = (double)L * (double)L * (double)L;
+        const double rho_c = (double)desc[r].rho_c;
+        double *gl = ws + s.glob_off;
+        gl[0] = tot[0] / N;               // dbar
+        gl[1] = rho_c + tot[0] / N;       // rho0
+        gl[2] = rho_c * N + tot[0];       // mass
+        gl[3] = tot[1];
+        gl[4] = tot[2];
+        gl[5] = tot[3];
+    }
+}
+
+// 5.-7. Box sums of drho and drho^2 at the finest level Lmin, separably:
+// along x from the snapshot, then along y, then along z.
+__global__ void __launch_bounds__(kBlock)
+k_box_x(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep,
+        const float *__restrict__ snap, double *__restrict__ ws) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= cum[nrep]) return;
+    const int r = find_cum(cum, nrep, g);
+    const SampDesc &s = sd[r];
+    const int64_t li = g - cum[r];          // (z, y, bx)
+    const int64_t row = li / s.nb, bx = li - row * s.nb;
+    const float *src = snap + s.site_off + row * s.L + bx * s.Lmin;
+    double a1 = 0.0, a2 = 0.0;
+    for (int i = 0; i < s.Lmin; ++i) {
+        const double v = (double)src[i];
+        a1 += v;
+        a2 += v * v;
+    }
+    const int64_t cnt = (int64_t)s.L * s.L * s.nb;
+    ws[s.a_off + li] = a1;
+    ws[s.a_off + cnt + li] = a2;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_box_y(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep, double *__restrict__ ws) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= cum[nrep]) return;
+    const int r = find_cum(cum, nrep, g);
+    const SampDesc &s = sd[r];
+    const int64_t li = g - cum[r];          // (z, by, bx)
+    const int nb = s.nb;
+    const int64_t z = li / ((int64_t)nb * nb);
+    const int64_t rem = li - z * nb * nb;
+    const int64_t by = rem / nb, bx = rem - by * nb;
+    const int64_t cntA = (int64_t)s.L * s.L * nb;
+    double a1 = 0.0, a2 = 0.0;
+    for (int i = 0; i < s.Lmin; ++i) {
+        const int64_t src = (z * s.L + by * s.Lmin + i) * nb + bx;
+        a1 += ws[s.a_off + src];
+        a2 += ws[s.a_off + cntA + src];
+    }
+    const int64_t cntB = (int64_t)s.L * nb * nb;
+    ws[s.b_off + li] = a1;
+    ws[s.b_off + cntB + li] = a2;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_box_z(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep, double *__restrict__ ws) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= cum[nrep]) return;
+    const int r = find_cum(cum, nrep, g);
+    const SampDesc &s = sd[r];
+    const int64_t li = g - cum[r];          // (bz, by, bx)
+    const int nb = s.nb;
+    const int64_t plane = (int64_t)nb * nb;
+    const int64_t bz = li / plane, rem = li - bz * plane;
+    const int64_t cntB = (int64_t)s.L * plane;
+    double a1 = 0.0, a2 = 0.0;
+    for (int i = 0; i < s.Lmin; ++i) {
+        const int64_t src = (bz * s.Lmin + i) * plane + rem;
+        a1 += ws[s.b_off + src];
+        a2 += ws[s.b_off + cntB + src];
+    }
+    const int64_t dst = s.lev_off[s.nlev - 1];
+    const int64_t cnt = plane * nb;
+    ws[dst + li] = a1;
+    ws[dst + cnt + li] = a2;
+}
+
+// 8. Level lev from its finer neighbour lev + 1: each box sums its 8 children.
+__global__ void __launch_bounds__(kBlock)
+k_coarsen(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep, int lev,
+          double *__restrict__ ws) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= cum[nrep]) return;
+    const int r = find_cum(cum, nrep, g);
+    const SampDesc &s = sd[r];
+    const int64_t li = g - cum[r];
+    const int64_t nc = s.L / s.lev_L[lev];  // boxes per axis, this level
+    const int64_t nf = 2 * nc;
+    const int64_t bz = li / (nc * nc), rem = li - bz * nc * nc;
+    const int64_t by = rem / nc, bx = rem - by * nc;
+    const double *fine = ws + s.lev_off[lev + 1];
+    const int64_t cntf = nf * nf * nf;
+    double a1 = 0.0, a2 = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int64_t src = (2 * bx + dx) + nf * ((2 * by + dy) + nf * (2 * bz + dz));
+                a1 += fine[src];
+                a2 += fine[cntf + src];
+            }
+    const int64_t cnt = nc * nc * nc;
+    ws[s.lev_off[lev] + li] = a1;
+    ws[s.lev_off[lev] + cnt + li] = a2;
+}
+
+// 9. Partial sums over a chunk of boxes of m, m^2, m^3, m^4, |m|, E, E^2.
+constexpr int kBoxesPerThread = 16;
+constexpr int kChunkBoxes = kBlock * kBoxesPerThread;
+
+__global__ void __launch_bounds__(kBlock)
+k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ chunks,
+                 double *__restrict__ ws, double *__restrict__ parts) {
+    __shared__ double sh[kBlock];
+    const BoxChunk c = chunks[blockIdx.x];
+    const SampDesc &s = sd[c.rep];
+    const double *gl = ws + s.glob_off;
+    const double dbar = gl[0], inv_rho0 = 1.0 / gl[1];
+    const int Lb = s.lev_L[c.lev];
+    const double n = (double)Lb * (double)Lb * (double)Lb;
+    const int64_t nbl = s.L / Lb;
+    const int64_t cnt = nbl * nbl * nbl;
+    const double *b1 = ws + s.lev_off[c.lev];
+    const double *b2 = b1 + cnt;
+    double acc[kMoments] = {0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < kBoxesPerThread; ++k) {
+        const int64_t i = (int64_t)k * kBlock + threadIdx.x;
+        if (i >= c.count) break;
+        const double B1 = b1[c.first + i], B2 = b2[c.first + i];
+        const double sphi = (B1 - n * dbar) * inv_rho0;
+        const double sphi2 = (B2 - 2.0 * dbar * B1 + n * dbar * dbar) * inv_rho0 * inv_rho0;
+        const double m = sphi / n, E = sphi2 / (2.0 * n);
+        const double m2 = m * m;
+        acc[0] += m;
+        acc[1] += m2;
+        acc[2] += m2 * m;
+        acc[3] += m2 * m2;
+        acc[4] += fabs(m);
+        acc[5] += E;
+        acc[6] += E * E;
+    }
+#pragma unroll
+    for (int q = 0; q < kMoments; ++q) {
+        const double v = block_sum(acc[q], sh);
+        if (threadIdx.x == 0) parts[(int64_t)blockIdx.x * kMoments + q] = v;
+    }
+}
+
+// 10. Per replica (one workgroup each): reduce the chunks of every level,
+// add to the accumulators, add the axis structure factor, append a series
+// record and count the sample.
+__global__ void __launch_bounds__(kBlock)
+k_finalize(const SampDesc *__restrict__ sd, double *__restrict__ ws, const double *__restrict__ parts,
+           double *__restrict__ acc_all, double *__restrict__ series_all, int64_t *__restrict__ nsamp,
+           const uint64_t *__restrict__ step, int koff) {
+    __shared__ double sh[kBlock];
+    __shared__ double lev_tot[kMaxLevels * kMoments];
+    const int r = blockIdx.x;
+    const SampDesc &s = sd[r];
+    const double *gl = ws + s.glob_off;
+    double *acc = acc_all + s.acc_off;
+    for (int lev = 0; lev < s.nlev; ++lev) {
+        for (int q = 0; q < kMoments; ++q) {
+            double v = 0.0;
+            for (int64_t k = threadIdx.x; k < s.chunk_count[lev]; k += kBlock)
+                v += parts[(s.chunk_first[lev] + k) * kMoments + q];
+            v = block_sum(v, sh);
+            if (threadIdx.x == 0) {
+                lev_tot[lev * kMoments + q] = v;
+                acc[lev * kMoments + q] += v;
+            }
+        }
+    }
+    // axis structure factor S_a(k_m) = N^-1 |sum_n P_a(n) e^{-i k_m n}|^2 of phi
+    const int L = s.L;
+    const double *planes = ws + s.planes_off;
+    const double rho0 = gl[1], dbar = gl[0];
+    const double Nsites = (double)L * L * L;
+    const double off = (double)L * L * dbar;  // plane sum of rho0 - rho_c
+    for (int idx = threadIdx.x; idx < 3 * s.n_k; idx += kBlock) {
+        const int a = idx / s.n_k, m = idx - a * s.n_k + 1;
+        double re = 0.0, im = 0.0;
+        for (int n = 0; n < L; ++n) {
+            const double p = (planes[a * L + n] - off) / rho0;
+            double sn, cs;
+            sincospi(2.0 * (double)((int64_t)m * n % L) / (double)L, &sn, &cs);
+            re += p * cs;
+            im -= p * sn;
+        }
+        acc[s.nlev * kMoments + idx] += (re * re + im * im) / Nsites;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t k = nsamp[r];
+        if (s.series_cap > 0) {
+            double *rec = series_all + s.series_off + (k % s.series_cap) * s.rec_len;
+            rec[0] = (double)(*step + (uint64_t)koff);
+            rec[1] = gl[2];
+            rec[2] = gl[3];
+            rec[3] = gl[4];
+            rec[4] = gl[5];
+            for (int lev = 0; lev < s.nlev; ++lev) {
+                const double nb = (double)(s.L / s.lev_L[lev]);
+                const double nboxes = nb * nb * nb;
+                for (int q = 0; q < kMoments; ++q)
+                    rec[5 + lev * kMoments + q] = lev_tot[lev * kMoments + q] / nboxes;
+            }
+        }
+        nsamp[r] = k + 1;
+    }
+}
+
+}  // namespace lbfss

@@ -1,0 +1,61 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no compute call: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1202_4748_amd as lbf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "lbfss.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lbf.library_path()):
+        from paper_1202_4748_amd import build
+        build.build()
+    return lbf.lib()
+
+
+def test_every_declared_symbol_exported(L):
+    names = declared()
+    assert set(names) == set(lbf.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror(L):
+    for code in (0, -1, -2, -3, -4, -5, 7):
+        assert isinstance(L.lb_strerror(code), bytes)
+    assert b"unstable" in L.lb_strerror(lbf.LB_EUNSTABLE)
+
+
+def test_invalid_arguments_rejected_before_device(L):
+    """Parameter validation happens on the host, before any HIP call."""
+    h = ctypes.c_void_p()
+    good = lbf.make_params(a=0.0, b=0.1, kappa=0.1, kT=1e-4, tau=1.0)
+    for L_, p in [(3, good), (2000, good),
+                  (16, lbf.make_params(tau=0.5)), (16, lbf.make_params(kT=-1.0)),
+                  (16, lbf.make_params(kappa=-0.1)), (16, lbf.make_params(b=-1.0)),
+                  (16, lbf.make_params(rho_c=0.0)), (16, lbf.make_params(init_sigma=-1.0)),
+                  (16, lbf.make_params(sample_every=-1)), (16, lbf.make_params(n_levels=-2))]:
+        assert L.lb_create(L_, ctypes.byref(p), 1, ctypes.byref(h)) == lbf.LB_EINVAL
+    bad = lbf.make_params()
+    bad.storage = 7
+    assert L.lb_create(16, ctypes.byref(bad), 1, ctypes.byref(h)) == lbf.LB_EINVAL
+    # mixed storage in one batch
+    Ls = (ctypes.c_int * 2)(8, 8)
+    P = (lbf.Params * 2)(lbf.make_params(storage="fp32"), lbf.make_params(storage="fp16"))
+    S = (ctypes.c_uint64 * 2)(1, 2)
+    assert L.lb_create_batch(2, Ls, P, S, ctypes.byref(h)) == lbf.LB_EINVAL
+    assert L.lb_step(None, 1) == lbf.LB_EINVAL
+    assert L.lb_sync(None) == lbf.LB_EINVAL
+    L.lb_destroy(None)

@@ -1,0 +1,89 @@
+"""GPU observables against the oracle's plain definitions, on the same seeded
+trajectories, and the mass / momentum budgets."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import moments
+from gpu_util import require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+M0 = workloads.MODEL
+
+
+def _oracle_run(L, seed, steps, every, n_levels, **prm):
+    orc = oracle.Sim(L, seed, **prm)
+    acc = moments.Accumulator(L, n_levels)
+    for t in range(steps):
+        orc.step(1)
+        if (t + 1) % every == 0:
+            rho, j = orc.fields()
+            acc.add(rho, step=t + 1, j=j)
+    return orc, acc
+
+
+@pytest.mark.parametrize("L,n_levels,every", [(16, 0, 1), (12, 0, 3), (24, 2, 2), (10, 1, 1)])
+def test_accumulators_match_oracle(L, n_levels, every):
+    lbf = require_gpu()
+    say(f"moments L={L} levels={n_levels} every={every}")
+    steps = 30
+    sim = lbf.Sim(L, 77, sample_every=every, n_levels=n_levels, series_capacity=64, **M0)
+    sim.step(steps)
+    got = sim.moments(series=True)
+    orc, acc = _oracle_run(L, 77, steps, every, n_levels, **M0)
+    assert got["n_samples"] == acc.n_samples == steps // every
+    assert [lv["Lb"] for lv in got["levels"]] == acc.levels
+    for lv in got["levels"]:
+        ref = acc.sums[lv["Lb"]]
+        assert lv["n_boxes"] == ref["n"]
+        for k in ("m2", "m4", "abs_m", "E", "E2", "m3"):
+            scale = max(abs(ref[k]), 1e-300)
+            # FP32 trajectories: moments of phi agree to ~1e-5 relative
+            assert abs(lv[k] - ref[k]) <= 2e-5 * scale + 1e-22, (lv["Lb"], k, lv[k], ref[k])
+        # boxes tile the lattice: sum of box means of phi is 0 up to rounding
+        assert abs(lv["m"]) < 1e-9
+    assert np.allclose(got["sk"], acc.sk, rtol=2e-5, atol=1e-16)
+    ser = got["series"]
+    assert ser.shape[0] == acc.n_samples
+    for i, rec in enumerate(acc.series):
+        assert ser[i, 0] == rec["step"]
+        assert abs(ser[i, 1] - rec["mass"]) < 1e-9 * rec["mass"]
+        assert np.allclose(ser[i, 2:5], rec["momentum"], atol=1e-8)
+        for li, Lb in enumerate(acc.levels):
+            for q, k in enumerate(moments.MOMENT_KEYS):
+                v, r = ser[i, 5 + 7 * li + q], rec[Lb][k]
+                assert abs(v - r) <= 2e-5 * abs(r) + (1e-9 if k == "m" else 1e-22), (i, Lb, k, v, r)
+
+
+def test_series_ring_wraps():
+    lbf = require_gpu()
+    say("series ring")
+    sim = lbf.Sim(8, 5, sample_every=1, series_capacity=4, **M0)
+    sim.step(10)
+    got = sim.moments(series=True)
+    assert got["n_samples"] == 10
+    assert list(got["series"][:, 0]) == [7, 8, 9, 10]
+    sim.reset_moments()
+    sim.step(2)
+    got = sim.moments(series=True)
+    assert got["n_samples"] == 2 and list(got["series"][:, 0]) == [11, 12]
+
+
+def test_mass_and_momentum_budget():
+    """Mass is conserved up to FP32 rounding (reported in FP64); for b = 0 the
+    total momentum stays zero up to rounding (exact conservation)."""
+    lbf = require_gpu()
+    say("budgets L=32")
+    for prm in (dict(M0, b=0.0, a=0.05), M0):
+        sim = lbf.Sim(32, 9, **prm)
+        m0 = sim.moments()
+        sim.step(500)
+        m1 = sim.moments()
+        N = 32 ** 3
+        drift = abs(m1["mass"] - m0["mass"]) / m0["mass"]
+        say(f"  b={prm['b']}: relative mass drift {drift:.2e}, momentum {m1['momentum']}")
+        assert drift < 500 * N ** 0.5 * 6e-8 / N + 1e-9
+        if prm["b"] == 0.0:
+            assert np.max(np.abs(m1["momentum"])) < 1e-4

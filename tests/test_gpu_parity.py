@@ -1,0 +1,182 @@
+"""GPU path against the FP64 oracle, element by element, through the C ABI.
+
+Tolerance (FP32 compute and storage against FP64): after every step, for each
+field X in {rho, j, f}: max |X_gpu - X_oracle| / max |X_oracle| <= 1e-5.
+FP16 storage rounds each stored deviation (f_i - w_i rho_c)/w_i to 11
+significant bits (relative 2^-11 of values up to ~0.05, an absolute 2.4e-5 of
+the deviation, 0.8e-5 of f); the rounding of successive steps accumulates as a
+random walk damped by the collision, so FP16 fields are held to 2e-4.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import dev_rel_err, rel_err, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL16 = 2e-4
+M0 = workloads.MODEL
+
+
+def _compare(sim, orc, tol, where, replica=0):
+    fg = sim.fields(replica, rho=True, j=True, f=True)
+    rho_o, j_o = orc.fields()
+    e = (rel_err(fg["rho"], rho_o), rel_err(fg["j"], j_o), rel_err(fg["f"], orc.f))
+    assert max(e) <= tol, f"{where}: rel errors rho/j/f = {e}"
+    return e
+
+
+def test_initial_state():
+    lbf = require_gpu()
+    say("initial state L=16")
+    sim = lbf.Sim(16, workloads.SEED, **M0)
+    orc = oracle.Sim(16, workloads.SEED, **M0)
+    _compare(sim, orc, 1e-7, "t=0")
+
+
+@pytest.mark.parametrize("kernel", ["split", "fused"])
+def test_config0_100_steps(kernel):
+    """16^3, a=0, b=0.1, kappa=0.1, kT=1e-4, tau=1: every step of 100."""
+    lbf = require_gpu()
+    say(f"config0 L=16 kernel={kernel}")
+    sim = lbf.Sim(16, workloads.SEED, **M0)
+    sim.set_plan(kernel, (16, 8, 8))
+    orc = oracle.Sim(16, workloads.SEED, **M0)
+    worst = 0.0
+    for t in range(100):
+        sim.step(1)
+        orc.step(1)
+        worst = max(worst, max(_compare(sim, orc, TOL32, f"step {t + 1}")))
+    rho_g = sim.fields()["rho"]
+    say(f"  worst field error {worst:.2e}, deviation-relative {dev_rel_err(rho_g, orc.rho()):.2e}")
+
+
+@pytest.mark.parametrize("L,tile", [(4, (4, 4, 4)), (7, (4, 4, 3)), (12, (8, 8, 5)), (20, (16, 8, 16)),
+                                    (37, (32, 8, 16))])
+def test_ragged_sizes(L, tile):
+    """Sizes not divisible by the tile (partial tiles, wrap-around halos)."""
+    lbf = require_gpu()
+    say(f"ragged L={L} tile={tile}")
+    prm = dict(M0, a=0.01, b=0.5, tau=0.8)
+    sim = lbf.Sim(L, 7 + L, **prm)
+    sim.set_plan("fused", tile)
+    orc = oracle.Sim(L, 7 + L, **prm)
+    for t in range(10):
+        sim.step(1)
+        orc.step(1)
+        _compare(sim, orc, TOL32, f"L={L} step {t + 1}")
+
+
+def test_strong_nonequilibrium_state():
+    """A far-from-equilibrium state (drho 0.05, u 0.03, random ghosts) through
+    the import path, with a strong quartic term."""
+    lbf = require_gpu()
+    L = 10
+    say("strong state L=10")
+    f0 = workloads.random_populations(L, 99, drho=0.05, u=0.03, neq=0.02)
+    prm = dict(a=-0.05, b=2.0, kappa=0.2, rho_c=1.0, kT=1e-4, tau=0.7)
+    for kernel in ("split", "fused"):
+        sim = lbf.Sim(L, 5, **prm)
+        sim.set_plan(kernel, (8, 4, 4))
+        sim.set_populations(f0)
+        orc = oracle.Sim(L, 5, f=f0, **prm)
+        _compare(sim, orc, 1e-6, f"{kernel} import")
+        for t in range(20):
+            sim.step(1)
+            orc.step(1)
+            _compare(sim, orc, TOL32, f"{kernel} step {t + 1}")
+
+
+def test_force_off_ideal_gas():
+    lbf = require_gpu()
+    say("force off L=12")
+    prm = dict(M0, force_off=True, tau=0.9)
+    sim = lbf.Sim(12, 3, **prm)
+    orc = oracle.Sim(12, 3, **prm)
+    sim.step(20)
+    orc.step(20)
+    _compare(sim, orc, TOL32, "force off")
+
+
+def test_fp16_storage():
+    lbf = require_gpu()
+    say("fp16 L=16")
+    sim = lbf.Sim(16, workloads.SEED, storage="fp16", **M0)
+    orc = oracle.Sim(16, workloads.SEED, **M0)
+    for t in range(100):
+        sim.step(1)
+        orc.step(1)
+        if (t + 1) % 10 == 0:
+            _compare(sim, orc, TOL16, f"fp16 step {t + 1}")
+
+
+def test_plans_bit_identical():
+    """Split, fused with different tiles and graph replay give the same bits."""
+    lbf = require_gpu()
+    L = 24
+    say("plans L=24")
+    states = []
+    for kernel, tile, g in [("split", (0, 0, 0), 0), ("fused", (16, 8, 8), 0), ("fused", (24, 24, 24), 0),
+                            ("fused", (8, 4, 5), 6), ("split", (0, 0, 0), 4)]:
+        sim = lbf.Sim(L, 11, **M0)
+        sim.set_plan(kernel, tile, g)
+        sim.step(13)
+        states.append(sim.fields(f=True)["f"])
+    for s in states[1:]:
+        assert np.array_equal(s, states[0])
+
+
+def test_deterministic_repeat():
+    lbf = require_gpu()
+    say("repeat L=16")
+    a = lbf.Sim(16, 1234, **M0)
+    b = lbf.Sim(16, 1234, **M0)
+    a.step(25)
+    b.step(25)
+    assert np.array_equal(a.fields(f=True)["f"], b.fields(f=True)["f"])
+    c = lbf.Sim(16, 1235, **M0)
+    c.step(25)
+    assert not np.array_equal(a.fields()["rho"], c.fields()["rho"])
+
+
+def test_batched_equals_plain():
+    """Every replica of a batch of uneven sizes and parameters evolves bit for
+    bit as it does alone."""
+    lbf = require_gpu()
+    say("batch vs plain")
+    Ls = [8, 12, 5, 16, 9]
+    seeds = [101, 102, 103, 104, 105]
+    prms = [dict(M0, a=a) for a in (-0.02, 0.0, 0.02, 0.01, -0.01)]
+    prms[2]["tau"] = 0.8
+    prms[3]["kT"] = 2e-4
+    bat = lbf.Sim.batch(Ls, seeds, prms)
+    bat.step(17)
+    for r, (L, sd, p) in enumerate(zip(Ls, seeds, prms)):
+        one = lbf.Sim(L, sd, **p)
+        one.step(17)
+        fb = bat.fields(r, f=True)["f"]
+        fo = one.fields(f=True)["f"]
+        assert np.array_equal(fb, fo), f"replica {r}"
+
+
+def test_unstable_flag_is_sticky():
+    """A negative density (the positivity condition of Sec. III B) raises
+    LB_EUNSTABLE at the next synchronisation, and stays raised."""
+    lbf = require_gpu()
+    say("unstable flag")
+    L = 6
+    f = workloads.random_populations(L, 1)
+    f[:, 0] = -np.abs(f[:, 0])   # site 0 with rho < 0
+    sim = lbf.Sim(L, 1, **M0)
+    sim.step(1)
+    sim.sync()
+    with pytest.raises(lbf.LBError) as e:
+        sim.set_populations(f)
+        sim.step(1)
+        sim.sync()
+    assert e.value.code == lbf.LB_EUNSTABLE
+    with pytest.raises(lbf.LBError):
+        sim.sync()

@@ -1,0 +1,57 @@
+"""Seeded synthetic inputs shared by the oracle side and the GPU side of the
+tests and the benchmark.  Parameter sets and random populations only: no
+arithmetic of the method lives here.
+
+The paper (Gross & Varnik) runs 2D D2Q9 simulations with parameter sets, not
+datasets; these 3D workloads replace them (sizes, run lengths, parameters).
+"""
+import numpy as np
+
+SEED = 20120221
+
+# GL parameters of the reference model: critical-point search around a = 0
+MODEL = dict(a=0.0, b=0.1, kappa=0.1, rho_c=1.0, kT=1e-4, tau=1.0, init_sigma=1e-3)
+
+WORKLOADS = {
+    # oracle-sized case: 16^3, 1000 steps
+    "d3q19_16": dict(L=16, steps=1000, **MODEL),
+    # 64^3 verification: Gaussian statics (b = 0, a > 0) against Ornstein-Zernike
+    "d3q19_64_oz": dict(L=64, steps=20000, **{**MODEL, "a": 0.05, "b": 0.0}),
+    "d3q19_64_crit": dict(L=64, steps=20000, **MODEL),
+    # plain 256^3 throughput case
+    "d3q19_256": dict(L=256, steps=5000, **MODEL),
+    # 512^3 precision variant
+    "d3q19_512_fp16": dict(L=512, steps=2000, storage="fp16", **MODEL),
+}
+
+
+def sweep_replicas(seeds_per_point=4):
+    """Finite-size sweep: L in {8,12,16,24,32,48} x a in {-0.02, -0.00667,
+    0.00667, 0.02} x 4 seeds = 96 replicas (b = 0.1, kappa = 0.1, kT = 1e-4)."""
+    Ls, seeds, params = [], [], []
+    k = 0
+    for L in (8, 12, 16, 24, 32, 48):
+        for a in (-0.02, -0.02 / 3, 0.02 / 3, 0.02):
+            for s in range(seeds_per_point):
+                Ls.append(L)
+                seeds.append(SEED + 1000 * k + s)
+                params.append({**MODEL, "a": a})
+            k += 1
+    return Ls, seeds, params
+
+
+def random_populations(L, seed, rho_c=1.0, drho=0.02, u=0.02, neq=0.01):
+    """A generic non-equilibrium state: w_i rho (1 + 3 c.u + ...) plus random
+    non-hydrodynamic parts, [19, L^3] doubles."""
+    rng = np.random.default_rng(seed)
+    N = L ** 3
+    C = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+                  (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
+                  (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)], float)
+    W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    rho = rho_c + drho * rng.standard_normal(N)
+    vel = u * rng.standard_normal((3, N))
+    cu = C @ vel
+    f = W[:, None] * rho * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * np.sum(vel * vel, axis=0))
+    f += neq * W[:, None] * rng.standard_normal((19, N))
+    return f
