@@ -198,19 +198,22 @@ void enqueue_totals(lb_sim *s, int cur) {
 
 void enqueue_sample(lb_sim *s, int cur, int koff) {
     enqueue_totals(s, cur);
-    hipLaunchKernelGGL(k_box_x, dim3((unsigned)ceil_div(s->n_bx, kBlock)), dim3(kBlock), 0, s->stream, s->d_sd,
-                       s->d_cum_bx, s->nrep, (const float *)s->d_snap, s->d_ws);
-    hipLaunchKernelGGL(k_box_y, dim3((unsigned)ceil_div(s->n_by, kBlock)), dim3(kBlock), 0, s->stream, s->d_sd,
-                       s->d_cum_by, s->nrep, s->d_ws);
-    hipLaunchKernelGGL(k_box_z, dim3((unsigned)ceil_div(s->n_bz, kBlock)), dim3(kBlock), 0, s->stream, s->d_sd,
-                       s->d_cum_bz, s->nrep, s->d_ws);
+    if (s->n_bx > 0) {
+        hipLaunchKernelGGL(k_box_x, dim3((unsigned)ceil_div(s->n_bx, kBlock)), dim3(kBlock), 0, s->stream,
+                           s->d_sd, s->d_cum_bx, s->nrep, (const float *)s->d_snap, s->d_ws);
+        hipLaunchKernelGGL(k_box_y, dim3((unsigned)ceil_div(s->n_by, kBlock)), dim3(kBlock), 0, s->stream,
+                           s->d_sd, s->d_cum_by, s->nrep, s->d_ws);
+        hipLaunchKernelGGL(k_box_z, dim3((unsigned)ceil_div(s->n_bz, kBlock)), dim3(kBlock), 0, s->stream,
+                           s->d_sd, s->d_cum_bz, s->nrep, s->d_ws);
+    }
     for (int lev = s->max_nlev - 2; lev >= 0; --lev) {
         if (s->n_coarse[lev] == 0) continue;
         hipLaunchKernelGGL(k_coarsen, dim3((unsigned)ceil_div(s->n_coarse[lev], kBlock)), dim3(kBlock), 0,
                            s->stream, s->d_sd, s->d_cum_coarse[lev], s->nrep, lev, s->d_ws);
     }
-    hipLaunchKernelGGL(k_level_partials, dim3(s->n_chunks), dim3(kBlock), 0, s->stream, s->d_sd, s->d_chunks,
-                       s->d_ws, s->d_parts);
+    if (s->n_chunks > 0)
+        hipLaunchKernelGGL(k_level_partials, dim3(s->n_chunks), dim3(kBlock), 0, s->stream, s->d_sd, s->d_chunks,
+                           s->d_ws, s->d_parts);
     hipLaunchKernelGGL(k_finalize, dim3(s->nrep), dim3(kBlock), 0, s->stream, s->d_sd, s->d_ws,
                        (const double *)s->d_parts, s->d_acc, s->d_series, s->d_nsamp, (const uint64_t *)s->d_step,
                        koff);
@@ -305,9 +308,11 @@ int build_sampling(lb_sim *s) {
         d.series_off = ser_len; ser_len += (int64_t)d.series_cap * d.rec_len;
         cum_rows.push_back(cum_rows.back() + LL);
         cum_cols.push_back(cum_cols.back() + LL);
-        cum_bx.push_back(cum_bx.back() + LL * d.nb);
-        cum_by.push_back(cum_by.back() + (int64_t)L * d.nb * d.nb);
-        cum_bz.push_back(cum_bz.back() + (int64_t)d.nb * d.nb * d.nb);
+        // a lattice without block levels (odd L) has no box work
+        const bool boxes = d.nlev > 0;
+        cum_bx.push_back(cum_bx.back() + (boxes ? LL * d.nb : 0));
+        cum_by.push_back(cum_by.back() + (boxes ? (int64_t)L * d.nb * d.nb : 0));
+        cum_bz.push_back(cum_bz.back() + (boxes ? (int64_t)d.nb * d.nb * d.nb : 0));
         for (int l = 0; l + 1 < s->max_nlev; ++l) {
             int64_t n = 0;
             if (l + 1 < d.nlev) {

@@ -113,10 +113,13 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
 // ---------------------------------------------------------------------------
 // Host side: tile tables and launch.
 // ---------------------------------------------------------------------------
+inline int fused_ep_max(int tx, int ty) { return (tx + 4) * (ty + 4); }
+constexpr int64_t kFusedLdsBytes = 65536;  // per workgroup: 4 density + 3 potential planes
+
 inline int make_fused_tiles(const std::vector<RepDesc> &reps, int tx, int ty, int tz,
                             std::vector<FusedTile> &out) {
     if (tx < 1 || ty < 1 || tz < 1 || tx > 256 || ty > 256 || tz > 1024) return -1;
-    if ((int64_t)(tx + 4) * (ty + 4) > 8192) return -1;  // LDS budget
+    if (7 * 4 * (int64_t)fused_ep_max(std::min(tx, 1024), std::min(ty, 1024)) > kFusedLdsBytes) return -1;
     out.clear();
     for (size_t r = 0; r < reps.size(); ++r) {
         const int L = reps[r].L;
@@ -129,8 +132,6 @@ inline int make_fused_tiles(const std::vector<RepDesc> &reps, int tx, int ty, in
     }
     return 0;
 }
-
-inline int fused_ep_max(int tx, int ty) { return (tx + 4) * (ty + 4); }
 
 inline void default_fused_tile(const std::vector<RepDesc> &reps, int &tx, int &ty, int &tz) {
     int maxL = 0;
@@ -156,7 +157,7 @@ inline std::vector<std::array<int, 3>> fused_tile_candidates(const std::vector<R
     std::vector<std::array<int, 3>> c = {{64, 8, 16}, {64, 16, 32}, {64, 8, 64}, {32, 8, 32},
                                          {128, 8, 32}, {64, 4, 32},  {32, 16, 16}};
     if (maxL <= 64) c.push_back({maxL, std::min(maxL, 16), std::min(maxL, 16)});
-    if (maxL <= 48) c.push_back({maxL, maxL, maxL});
+    if (maxL <= 44) c.push_back({maxL, maxL, maxL});
     return c;
 }
 

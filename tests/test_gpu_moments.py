@@ -37,24 +37,31 @@ def test_accumulators_match_oracle(L, n_levels, every):
     assert [lv["Lb"] for lv in got["levels"]] == acc.levels
     for lv in got["levels"]:
         ref = acc.sums[lv["Lb"]]
-        assert lv["n_boxes"] == ref["n"]
+        assert lv["n_boxes"] * got["n_samples"] == ref["n"]
         for k in ("m2", "m4", "abs_m", "E", "E2", "m3"):
-            scale = max(abs(ref[k]), 1e-300)
-            # FP32 trajectories: moments of phi agree to ~1e-5 relative
+            # FP32 trajectories: moments of phi agree to ~1e-5 relative; the odd
+            # moment m^3 nearly cancels, so it is held to the scale <m^2>^(3/2)
+            n = ref["n"]
+            scale = n * (ref["m2"] / n) ** 1.5 if k == "m3" else abs(ref[k])
             assert abs(lv[k] - ref[k]) <= 2e-5 * scale + 1e-22, (lv["Lb"], k, lv[k], ref[k])
         # boxes tile the lattice: sum of box means of phi is 0 up to rounding
         assert abs(lv["m"]) < 1e-9
     assert np.allclose(got["sk"], acc.sk, rtol=2e-5, atol=1e-16)
     ser = got["series"]
     assert ser.shape[0] == acc.n_samples
+    # total momentum sums N per-site values whose FP32 trajectory differs from
+    # the FP64 one by ~1e-7 of max |j|; the differences add up like sqrt(N)
+    jscale = np.max(np.abs(orc.fields()[1]))
+    ptol = 5 * np.sqrt(L ** 3) * 1e-7 * jscale
     for i, rec in enumerate(acc.series):
         assert ser[i, 0] == rec["step"]
         assert abs(ser[i, 1] - rec["mass"]) < 1e-9 * rec["mass"]
-        assert np.allclose(ser[i, 2:5], rec["momentum"], atol=1e-8)
+        assert np.max(np.abs(ser[i, 2:5] - rec["momentum"])) < ptol, (i, ser[i, 2:5], rec["momentum"], ptol)
         for li, Lb in enumerate(acc.levels):
             for q, k in enumerate(moments.MOMENT_KEYS):
                 v, r = ser[i, 5 + 7 * li + q], rec[Lb][k]
-                assert abs(v - r) <= 2e-5 * abs(r) + (1e-9 if k == "m" else 1e-22), (i, Lb, k, v, r)
+                scale = rec[Lb]["m2"] ** 1.5 if k == "m3" else abs(r)
+                assert abs(v - r) <= 2e-5 * scale + (1e-9 if k == "m" else 1e-22), (i, Lb, k, v, r)
 
 
 def test_series_ring_wraps():

@@ -2,10 +2,15 @@
 
 Tolerance (FP32 compute and storage against FP64): after every step, for each
 field X in {rho, j, f}: max |X_gpu - X_oracle| / max |X_oracle| <= 1e-5.
-FP16 storage rounds each stored deviation (f_i - w_i rho_c)/w_i to 11
-significant bits (relative 2^-11 of values up to ~0.05, an absolute 2.4e-5 of
-the deviation, 0.8e-5 of f); the rounding of successive steps accumulates as a
-random walk damped by the collision, so FP16 fields are held to 2e-4.
+
+FP16 storage rounds each stored deviation r_i = (f_i - w_i rho_c)/w_i
+(|r| <~ 0.1) to 11 significant bits: at most 2^-15 = 3e-5 absolute per
+population and step.  Through sum_i w_i c_i r_i that is <= 1e-5 absolute in a
+momentum component per step (about 3e-4 of max |j| ~ 0.03 at kT = 1e-4), and
+<= 3e-5 in rho (3e-5 of max rho ~ 1).  Momentum is conserved, so these
+roundings random-walk: after n steps the error grows like sqrt(n) times the
+typical (about a third of the worst) step error.  Over 100 steps the FP16
+bounds are 3e-3 for j and 3e-4 for rho and f.
 """
 import numpy as np
 import pytest
@@ -17,7 +22,7 @@ from gpu_util import dev_rel_err, rel_err, require_gpu, say
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
-TOL16 = 2e-4
+TOL16 = {"rho": 3e-4, "j": 3e-3, "f": 3e-4}
 M0 = workloads.MODEL
 
 
@@ -25,7 +30,11 @@ def _compare(sim, orc, tol, where, replica=0):
     fg = sim.fields(replica, rho=True, j=True, f=True)
     rho_o, j_o = orc.fields()
     e = (rel_err(fg["rho"], rho_o), rel_err(fg["j"], j_o), rel_err(fg["f"], orc.f))
-    assert max(e) <= tol, f"{where}: rel errors rho/j/f = {e}"
+    if isinstance(tol, dict):
+        ok = e[0] <= tol["rho"] and e[1] <= tol["j"] and e[2] <= tol["f"]
+    else:
+        ok = max(e) <= tol
+    assert ok, f"{where}: rel errors rho/j/f = {e}"
     return e
 
 
@@ -106,11 +115,14 @@ def test_fp16_storage():
     say("fp16 L=16")
     sim = lbf.Sim(16, workloads.SEED, storage="fp16", **M0)
     orc = oracle.Sim(16, workloads.SEED, **M0)
+    worst = (0.0, 0.0, 0.0)
     for t in range(100):
         sim.step(1)
         orc.step(1)
         if (t + 1) % 10 == 0:
-            _compare(sim, orc, TOL16, f"fp16 step {t + 1}")
+            e = _compare(sim, orc, TOL16, f"fp16 step {t + 1}")
+            worst = tuple(max(a, b) for a, b in zip(worst, e))
+    say(f"  fp16 worst rel errors rho/j/f = {worst}")
 
 
 def test_plans_bit_identical():
