@@ -63,10 +63,11 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        // one 32x32 -> 64-bit multiply-add instruction per product
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c0 = hi1 ^ c1 ^ k0;
         c1 = lo1;
         c2 = hi0 ^ c3 ^ k1;
@@ -157,7 +158,7 @@ __device__ __forceinline__ float collide_site(const RepDesc &d, float (&r)[Q], f
     const float m18 = sZ - sY + (sA + sB) - (sC + sD);
 
     const float rho = d.rho_c + drho;
-    const float inv_rho = 1.0f / rho;
+    const float inv_rho = __builtin_amdgcn_rcpf(rho);  // hardware reciprocal, 1 ulp
     const float ux = (jx + 0.5f * Fx) * inv_rho;
     const float uy = (jy + 0.5f * Fy) * inv_rho;
     const float uz = (jz + 0.5f * Fz) * inv_rho;

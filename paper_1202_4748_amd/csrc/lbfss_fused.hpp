@@ -1,12 +1,20 @@
-// Fused step: one pass per time step.  A workgroup owns an x-y tile of one
-// replica and marches through a range of z planes.  For each plane it pulls
-// the populations of the tile plus a two-site halo to form the density in
-// LDS (a four-plane ring), derives the chemical potential on the tile plus
-// a one-site halo (a three-plane ring), and two planes behind that front
-// collides the tile interior: force from the LDS stencils, pull, moment-space
-// collision with Philox noise, store.  Densities of the halo are recomputed
-// by neighbouring tiles instead of being exchanged, so there is no
-// inter-workgroup synchronisation; the halo pulls mostly hit L2.
+// Fused step: one pass per time step.
+//
+// A 256-thread workgroup owns an x-y tile of TX x TY = 256 sites of one
+// replica and marches through a range of z planes, one thread per tile site.
+// For each plane p it
+//   (a) pulls the 19 populations of its site into a register ring (three
+//       planes deep) and puts the site density in an LDS ring; threads also
+//       pull the two-site halo of the tile, for the density only;
+//   (b) derives the chemical potential of plane p - 1 on the tile and a
+//       one-site halo (LDS ring);
+//   (c) collides plane p - 2 from the register ring: force from the LDS
+//       stencils, moment-space collision with Philox noise, store.
+// Populations are read from memory once per site; the halo pulls are
+// interior pulls of a neighbouring tile, which the XCD-aware workgroup order
+// schedules on the same XCD at the same time, so they are served by its L2.
+// Address arithmetic is hoisted: per-plane offsets are wave-uniform and the
+// in-plane offsets of a thread are computed once.
 #pragma once
 
 #include <array>
@@ -22,90 +30,221 @@ struct FusedTile {
 
 __device__ __forceinline__ int wrap_near(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
 
+// In-plane byte offsets of the nine (x, y) positions a pull touches, for a
+// site at (x, y) of an L x L plane: centre, -x, +x, -y, +y and the four
+// diagonals.  Plane bases live in wave-uniform pointers, so every load is a
+// scalar base plus one of these 32-bit offsets.
+struct PlaneOffs {
+    uint32_t c, xm, xp, ym, yp, mm, pp, mp, pm;  // mm = (x-1, y-1), mp = (x-1, y+1), ...
+    __device__ __forceinline__ void set(int x, int y, int L, uint32_t esize) {
+        const uint32_t xm_ = wrap_dec(x, L), xp_ = wrap_inc(x, L);
+        const uint32_t Y0 = y * L, Ym = wrap_dec(y, L) * L, Yp = wrap_inc(y, L) * L;
+        c = (x + Y0) * esize;
+        xm = (xm_ + Y0) * esize;
+        xp = (xp_ + Y0) * esize;
+        ym = (x + Ym) * esize;
+        yp = (x + Yp) * esize;
+        mm = (xm_ + Ym) * esize;
+        pp = (xp_ + Yp) * esize;
+        mp = (xm_ + Yp) * esize;
+        pm = (xp_ + Ym) * esize;
+    }
+};
+
 template <typename T>
+__device__ __forceinline__ float ldb(const T *p, uint32_t boff) {
+    return Store<T>::ld((const T *)((const char *)p + boff), 0);
+}
+template <typename T>
+__device__ __forceinline__ void stb(T *p, uint32_t boff, float v) {
+    Store<T>::st((T *)((char *)p + boff), 0, v);
+}
+
+// Pull of the 19 populations of a site of plane z: buf_q(x - c_q).  qz[q] is
+// the base of population q shifted to plane z - cz_q (wave-uniform).
+template <typename T>
+__device__ __forceinline__ void pull_plane(const T *const (&qz)[Q], const PlaneOffs &o, float (&r)[Q]) {
+    r[0] = ldb(qz[0], o.c);
+    r[1] = ldb(qz[1], o.xm);
+    r[2] = ldb(qz[2], o.xp);
+    r[3] = ldb(qz[3], o.ym);
+    r[4] = ldb(qz[4], o.yp);
+    r[5] = ldb(qz[5], o.c);
+    r[6] = ldb(qz[6], o.c);
+    r[7] = ldb(qz[7], o.mm);
+    r[8] = ldb(qz[8], o.pp);
+    r[9] = ldb(qz[9], o.mp);
+    r[10] = ldb(qz[10], o.pm);
+    r[11] = ldb(qz[11], o.xm);
+    r[12] = ldb(qz[12], o.xp);
+    r[13] = ldb(qz[13], o.xm);
+    r[14] = ldb(qz[14], o.xp);
+    r[15] = ldb(qz[15], o.ym);
+    r[16] = ldb(qz[16], o.yp);
+    r[17] = ldb(qz[17], o.ym);
+    r[18] = ldb(qz[18], o.yp);
+}
+
+// Workgroup index to tile index: each XCD (workgroups are dealt to the 8
+// XCDs round-robin) gets one contiguous run of the tile table, whose tiles
+// are ordered x fastest, then y, then z, so neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nt) {
+    const int per = nt / 8;
+    if (b >= per * 8) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename T, int TX>
 __global__ void __launch_bounds__(kBlock)
 k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const T *__restrict__ pop,
-        T *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err,
-        int ep_max) {
-    extern __shared__ float lds[];
-    const FusedTile tl = tiles[blockIdx.x];
+        T *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err) {
+    constexpr int TY = kBlock / TX;
+    constexpr int EX = TX + 4, EP = EX * (TY + 4);
+    constexpr int MX = TX + 2, MP = MX * (TY + 2);
+    __shared__ float s_rho[5][EP];
+    __shared__ float s_mu[4][MP];
+
+    const FusedTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const RepDesc &d = desc[tl.rep];
     const int L = d.L;
-    const int EX = tl.nx + 4, EP = EX * (tl.ny + 4);
-    const int MX = tl.nx + 2, MP = MX * (tl.ny + 2);
-    float *rho_ring = lds;                 // 4 planes of EP (stride ep_max)
-    float *mu_ring = lds + 4 * ep_max;     // 3 planes of MP (stride ep_max)
+    const uint32_t N = (uint32_t)d.N, LL = (uint32_t)(L * L);
     const T *base = pop + Q * d.site_off;
     T *obase = pop_out + Q * d.site_off;
     const uint64_t t = *step + (uint64_t)koff;
     const bool force_on = !(d.flags & 1);
-    bool bad = false;
 
-    for (int p = tl.z0 - 2; p <= tl.z0 + tl.nz + 1; ++p) {
-        // (a) density of plane p on the tile and its two-site halo
+    const int tid = threadIdx.x;
+    const int ix = tid % TX, iy = tid / TX;
+    const int nx = tl.nx, ny = tl.ny;
+    const bool inner = ix < nx && iy < ny;
+    const int sx = tl.x0 + (inner ? ix : 0), sy = tl.y0 + (inner ? iy : 0);
+    const uint32_t site_c = (uint32_t)(sx + sy * L);  // in-plane site index (noise counter)
+    PlaneOffs io;
+    io.set(sx, sy, L, sizeof(T));
+    const int r_in = (iy + 2) * EX + (ix + 2);  // LDS density index of the site
+    const int m_in = (iy + 1) * MX + (ix + 1);  // LDS potential index of the site
+
+    // density halo: ring of the (nx+4) x (ny+4) extension, one site per thread
+    const int ew = nx + 4;
+    const int nhalo = 4 * (nx + ny) + 16;
+    const bool has_h = tid < nhalo;
+    int hx = 0, hy = 0;
+    if (has_h) {
+        int h = tid;
+        if (h < 2 * ew) {
+            hy = h / ew;
+            hx = h - hy * ew;
+        } else if (h < 4 * ew) {
+            h -= 2 * ew;
+            hy = ny + 2 + h / ew;
+            hx = h - (h / ew) * ew;
+        } else {
+            h -= 4 * ew;
+            hy = 2 + (h >> 2);
+            const int k = h & 3;
+            hx = k < 2 ? k : nx + k;
+        }
+    }
+    PlaneOffs ho;
+    ho.set(wrap_near(tl.x0 - 2 + hx, L), wrap_near(tl.y0 - 2 + hy, L), L, sizeof(T));
+    const int r_h = hy * EX + hx;
+
+    // potential halo: ring of the (nx+2) x (ny+2) extension
+    const int mw = nx + 2;
+    const int nmhalo = 2 * (nx + ny) + 4;
+    const bool has_mh = tid < nmhalo;
+    int mhx = 0, mhy = 0;
+    if (has_mh) {
+        int h = tid;
+        if (h < mw) {
+            mhy = 0;
+            mhx = h;
+        } else if (h < 2 * mw) {
+            mhy = ny + 1;
+            mhx = h - mw;
+        } else {
+            h -= 2 * mw;
+            mhy = 1 + (h >> 1);
+            mhx = (h & 1) ? nx + 1 : 0;
+        }
+    }
+    const int m_h = mhy * MX + mhx;
+    const int r_mh = (mhy + 1) * EX + (mhx + 1);
+
+    bool bad = false;
+    float A[Q], B[Q], C[Q];
+
+    auto body = [&](int p, float(&ld)[Q], float(&cl)[Q]) {
+        // (a) density of plane p
         {
-            const int zp = wrap_near(p, L);
-            float *rs = rho_ring + ((p + 8) & 3) * ep_max;
-            for (int i = threadIdx.x; i < EP; i += kBlock) {
-                const int ey = i / EX, ex = i - ey * EX;
-                const Nbr n(wrap_near(tl.x0 - 2 + ex, L), wrap_near(tl.y0 - 2 + ey, L), zp, L);
-                float f[Q];
-                pull(base, d.N, n, f);
-                rs[i] = drho_of(f);
-            }
-        }
-        __syncthreads();
-        // (b) chemical potential of plane p - 1 on the tile and a one-site halo
-        if (p - 1 >= tl.z0 - 1) {
-            const float *rz[3] = {rho_ring + ((p - 2 + 8) & 3) * ep_max, rho_ring + ((p - 1 + 8) & 3) * ep_max,
-                                  rho_ring + ((p + 8) & 3) * ep_max};
-            float *ms = mu_ring + ((p - 1 + 9) % 3) * ep_max;
-            for (int i = threadIdx.x; i < MP; i += kBlock) {
-                const int my = i / MX, mx = i - my * MX;
-                const int c0 = (my + 1) * EX + (mx + 1);
-                const float c = rz[1][c0];
-                ms[i] = chem_potential(d, c, lap18(c, [&](int dx, int dy, int dz) {
-                                           return rz[1 + dz][c0 + dy * EX + dx];
-                                       }));
-            }
-        }
-        __syncthreads();
-        // (c) collide plane z = p - 2
-        if (p - 2 >= tl.z0) {
-            const int z = p - 2;
-            const float *rz[3] = {rho_ring + ((z - 1 + 8) & 3) * ep_max, rho_ring + ((z + 8) & 3) * ep_max,
-                                  rho_ring + ((z + 1 + 8) & 3) * ep_max};
-            const float *mz[3] = {mu_ring + ((z - 1 + 9) % 3) * ep_max, mu_ring + ((z + 9) % 3) * ep_max,
-                                  mu_ring + ((z + 1 + 9) % 3) * ep_max};
-            const int npl = tl.nx * tl.ny;
-            for (int i = threadIdx.x; i < npl; i += kBlock) {
-                const int iy = i / tl.nx, ix = i - iy * tl.nx;
-                const int x = tl.x0 + ix, y = tl.y0 + iy;
-                float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-                if (force_on) {
-                    const int rc0 = (iy + 2) * EX + (ix + 2);
-                    const int mc0 = (iy + 1) * MX + (ix + 1);
-                    const float rho_x = d.rho_c + rz[1][rc0];
-                    const Grad18 gr = grad18([&](int dx, int dy, int dz) {
-                        return (1.0f / 3.0f) * rz[1 + dz][rc0 + dy * EX + dx] -
-                               rho_x * mz[1 + dz][mc0 + dy * MX + dx];
-                    });
-                    Fx = gr.gx;
-                    Fy = gr.gy;
-                    Fz = gr.gz;
-                }
-                const Nbr n(x, y, z, L);
-                float f[Q];
-                pull(base, d.N, n, f);
-                const uint32_t s = (uint32_t)(x + n.Y0 + n.Z0);
-                const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
-                const float rho = collide_site(d, f, Fx, Fy, Fz, noise);
-                bad |= !(rho > 0.0f && rho < 1e30f);  // Sec. III B: rho must stay positive
+            const int zc = wrap_near(p, L);
+            const uint32_t Zc = (uint32_t)zc * LL, Zm = (uint32_t)wrap_dec(zc, L) * LL,
+                           Zp = (uint32_t)wrap_inc(zc, L) * LL;
+            const T *qz[Q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) Store<T>::st(obase + q * d.N, s, f[q]);
+            for (int q = 0; q < Q; ++q) {
+                const int cz = cz_of(q);
+                qz[q] = base + (size_t)q * N + (cz > 0 ? Zm : (cz < 0 ? Zp : Zc));
+            }
+            float *rs = s_rho[(p + 10) % 5];
+            if (inner) {
+                pull_plane(qz, io, ld);
+                rs[r_in] = drho_of(ld);
+            }
+            if (has_h) {
+                float h[Q];
+                pull_plane(qz, ho, h);
+                rs[r_h] = drho_of(h);
             }
         }
         __syncthreads();
+        // (b) chemical potential of plane p - 1
+        if (p - 1 >= tl.z0 - 1) {
+            const float *r0 = s_rho[(p - 2 + 10) % 5], *r1 = s_rho[(p - 1 + 10) % 5], *r2 = s_rho[(p + 10) % 5];
+            float *ms = s_mu[(p - 1 + 8) & 3];
+            auto mu_at = [&](int ri) {
+                const float c = r1[ri];
+                return chem_potential(d, c, lap18(c, [&](int dx, int dy, int dz) {
+                                          const float *pl = dz < 0 ? r0 : (dz > 0 ? r2 : r1);
+                                          return pl[ri + dy * EX + dx];
+                                      }));
+            };
+            if (inner) ms[m_in] = mu_at(r_in);
+            if (has_mh) ms[m_h] = mu_at(r_mh);
+        }
+        __syncthreads();
+        // (c) collision of plane z = p - 2
+        if (p - 2 >= tl.z0 && inner) {
+            const int z = p - 2;
+            float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+            if (force_on) {
+                const float *rm = s_rho[(z - 1 + 10) % 5], *rc = s_rho[(z + 10) % 5], *rp = s_rho[(z + 1 + 10) % 5];
+                const float *mm = s_mu[(z - 1 + 8) & 3], *mc = s_mu[(z + 8) & 3], *mp = s_mu[(z + 1 + 8) & 3];
+                const float rho_x = d.rho_c + rc[r_in];
+                const Grad18 gr = grad18([&](int dx, int dy, int dz) {
+                    const float *rr = dz < 0 ? rm : (dz > 0 ? rp : rc);
+                    const float *mu = dz < 0 ? mm : (dz > 0 ? mp : mc);
+                    return (1.0f / 3.0f) * rr[r_in + dy * EX + dx] - rho_x * mu[m_in + dy * MX + dx];
+                });
+                Fx = gr.gx;
+                Fy = gr.gy;
+                Fz = gr.gz;
+            }
+            const uint32_t s = site_c + (uint32_t)z * LL;
+            const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
+            const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
+            bad |= !(rho > 0.0f && rho < 1e30f);  // Sec. III B: rho must stay positive
+            T *oz = obase + (uint32_t)z * LL;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) stb(oz + (size_t)q * N, io.c, cl[q]);
+        }
+    };
+
+    const int p0 = tl.z0 - 2, pend = tl.z0 + tl.nz + 1;
+    for (int p = p0; p <= pend; p += 3) {
+        body(p, A, B);
+        if (p + 1 <= pend) body(p + 1, B, C);
+        if (p + 2 <= pend) body(p + 2, C, A);
     }
     if (bad) *err = 1;
 }
@@ -113,13 +252,11 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
 // ---------------------------------------------------------------------------
 // Host side: tile tables and launch.
 // ---------------------------------------------------------------------------
-inline int fused_ep_max(int tx, int ty) { return (tx + 4) * (ty + 4); }
-constexpr int64_t kFusedLdsBytes = 65536;  // per workgroup: 4 density + 3 potential planes
+inline bool fused_tile_ok(int tx, int ty) { return (tx == 16 && ty == 16) || (tx == 32 && ty == 8); }
 
 inline int make_fused_tiles(const std::vector<RepDesc> &reps, int tx, int ty, int tz,
                             std::vector<FusedTile> &out) {
-    if (tx < 1 || ty < 1 || tz < 1 || tx > 256 || ty > 256 || tz > 1024) return -1;
-    if (7 * 4 * (int64_t)fused_ep_max(std::min(tx, 1024), std::min(ty, 1024)) > kFusedLdsBytes) return -1;
+    if (!fused_tile_ok(tx, ty) || tz < 1 || tz > 1024) return -1;
     out.clear();
     for (size_t r = 0; r < reps.size(); ++r) {
         const int L = reps[r].L;
@@ -136,38 +273,34 @@ inline int make_fused_tiles(const std::vector<RepDesc> &reps, int tx, int ty, in
 inline void default_fused_tile(const std::vector<RepDesc> &reps, int &tx, int &ty, int &tz) {
     int maxL = 0;
     for (const auto &d : reps) maxL = std::max(maxL, d.L);
-    if (maxL >= 128) {
-        tx = 64;
-        ty = 16;
-        tz = 32;
-    } else if (maxL >= 64) {
-        tx = 64;
-        ty = 8;
-        tz = 16;
-    } else {
-        tx = std::min(maxL, 32);
-        ty = std::min(maxL, 8);
-        tz = std::min(maxL, 16);
-    }
+    tx = 32;
+    ty = 8;
+    tz = maxL >= 128 ? 32 : std::min(maxL, 16);
 }
 
 inline std::vector<std::array<int, 3>> fused_tile_candidates(const std::vector<RepDesc> &reps) {
     int maxL = 0;
     for (const auto &d : reps) maxL = std::max(maxL, d.L);
-    std::vector<std::array<int, 3>> c = {{64, 8, 16}, {64, 16, 32}, {64, 8, 64}, {32, 8, 32},
-                                         {128, 8, 32}, {64, 4, 32},  {32, 16, 16}};
-    if (maxL <= 64) c.push_back({maxL, std::min(maxL, 16), std::min(maxL, 16)});
-    if (maxL <= 44) c.push_back({maxL, maxL, maxL});
+    std::vector<std::array<int, 3>> c;
+    for (int tz : {16, 32, 64})
+        if (tz <= std::max(maxL, 16)) {
+            c.push_back({32, 8, tz});
+            c.push_back({16, 16, tz});
+        }
+    if (maxL < 16) c.push_back({16, 16, maxL});
     return c;
 }
 
 template <typename T>
 void launch_fused(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const T *in, T *out,
                   const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream) {
-    const int ep = fused_ep_max(tx, ty);
-    const size_t lds = sizeof(float) * (size_t)(7 * ep);
-    hipLaunchKernelGGL(k_fused<T>, dim3(n_tiles), dim3(kBlock), lds, stream, desc, tiles, in, out, step, koff,
-                       err, ep);
+    (void)ty;
+    if (tx == 16)
+        hipLaunchKernelGGL((k_fused<T, 16>), dim3(n_tiles), dim3(kBlock), 0, stream, desc, tiles, in, out, step,
+                           koff, err);
+    else
+        hipLaunchKernelGGL((k_fused<T, 32>), dim3(n_tiles), dim3(kBlock), 0, stream, desc, tiles, in, out, step,
+                           koff, err);
 }
 
 }  // namespace lbfss

@@ -52,7 +52,7 @@ def test_config0_100_steps(kernel):
     lbf = require_gpu()
     say(f"config0 L=16 kernel={kernel}")
     sim = lbf.Sim(16, workloads.SEED, **M0)
-    sim.set_plan(kernel, (16, 8, 8))
+    sim.set_plan(kernel, (16, 16, 8))
     orc = oracle.Sim(16, workloads.SEED, **M0)
     worst = 0.0
     for t in range(100):
@@ -63,8 +63,8 @@ def test_config0_100_steps(kernel):
     say(f"  worst field error {worst:.2e}, deviation-relative {dev_rel_err(rho_g, orc.rho()):.2e}")
 
 
-@pytest.mark.parametrize("L,tile", [(4, (4, 4, 4)), (7, (4, 4, 3)), (12, (8, 8, 5)), (20, (16, 8, 16)),
-                                    (37, (32, 8, 16))])
+@pytest.mark.parametrize("L,tile", [(4, (16, 16, 4)), (7, (32, 8, 3)), (12, (16, 16, 5)), (20, (16, 16, 16)),
+                                    (37, (32, 8, 16)), (40, (32, 8, 7))])
 def test_ragged_sizes(L, tile):
     """Sizes not divisible by the tile (partial tiles, wrap-around halos)."""
     lbf = require_gpu()
@@ -89,7 +89,7 @@ def test_strong_nonequilibrium_state():
     prm = dict(a=-0.05, b=2.0, kappa=0.2, rho_c=1.0, kT=1e-4, tau=0.7)
     for kernel in ("split", "fused"):
         sim = lbf.Sim(L, 5, **prm)
-        sim.set_plan(kernel, (8, 4, 4))
+        sim.set_plan(kernel, (16, 16, 4))
         sim.set_populations(f0)
         orc = oracle.Sim(L, 5, f=f0, **prm)
         _compare(sim, orc, 1e-6, f"{kernel} import")
@@ -131,8 +131,8 @@ def test_plans_bit_identical():
     L = 24
     say("plans L=24")
     states = []
-    for kernel, tile, g in [("split", (0, 0, 0), 0), ("fused", (16, 8, 8), 0), ("fused", (24, 24, 24), 0),
-                            ("fused", (8, 4, 5), 6), ("split", (0, 0, 0), 4)]:
+    for kernel, tile, g in [("split", (0, 0, 0), 0), ("fused", (16, 16, 8), 0), ("fused", (32, 8, 24), 0),
+                            ("fused", (32, 8, 5), 6), ("split", (0, 0, 0), 4)]:
         sim = lbf.Sim(L, 11, **M0)
         sim.set_plan(kernel, tile, g)
         sim.step(13)
