@@ -128,13 +128,16 @@ typedef struct {
 
 /* launch plans (results do not depend on the plan) */
 enum {
-    LB_KERNEL_SPLIT = 0, /* density pass, chemical-potential pass, collide pass */
-    LB_KERNEL_FUSED = 1  /* one z-marching pass with the density halo in LDS */
+    LB_KERNEL_SPLIT = 0,  /* density pass, chemical-potential pass, collide pass */
+    LB_KERNEL_FUSED = 1,  /* one z-marching pass, density halo in LDS, pulls in registers */
+    LB_KERNEL_STAGED = 2  /* as FUSED, the next plane's pulls staged asynchronously in LDS
+                           * (FP32 storage; FP16 handles run FUSED) */
 };
 
 typedef struct {
-    int32_t kernel;      /* LB_KERNEL_SPLIT or LB_KERNEL_FUSED */
-    int32_t tile_x;      /* fused: tile edge along x (sites), <= L is clamped */
+    int32_t kernel;      /* LB_KERNEL_SPLIT, LB_KERNEL_FUSED or LB_KERNEL_STAGED */
+    int32_t tile_x;      /* fused: tile edge along x; (tile_x, tile_y) in {(32,8), (16,16),
+                          * (16,8), (64,4)}, (64,4) not staged; clamped to L */
     int32_t tile_y;      /* fused: tile edge along y */
     int32_t tile_z;      /* fused: planes marched by one workgroup */
     int32_t graph_steps; /* > 0: capture this many steps (rounded up to even) in a

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lbfss.h"
@@ -158,7 +159,12 @@ template <typename T>
 void launch_step(lb_sim *s, int cur, int koff) {
     const T *in = (const T *)s->pop[cur];
     T *out = (T *)s->pop[cur ^ 1];
-    if (s->plan.kernel == LB_KERNEL_FUSED && s->n_tiles > 0) {
+    if (s->plan.kernel == LB_KERNEL_STAGED && s->n_tiles > 0 && std::is_same<T, float>::value) {
+        launch_fused_staged(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out, s->d_step, koff,
+                            s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream);
+        return;
+    }
+    if ((s->plan.kernel == LB_KERNEL_FUSED || s->plan.kernel == LB_KERNEL_STAGED) && s->n_tiles > 0) {
         launch_fused<T>(s->d_desc, s->d_tiles, s->n_tiles, in, out, s->d_step, koff, s->d_err,
                         s->plan.tile_x, s->plan.tile_y, s->stream);
         return;
@@ -661,7 +667,8 @@ int lb_set_plan(lb_sim *s, const lb_plan *plan) {
         const int64_t P = graph_period(s);
         p.graph_steps = (int)(ceil_div(p.graph_steps, P) * P);
     }
-    if (p.kernel == LB_KERNEL_FUSED) {
+    if (p.kernel == LB_KERNEL_FUSED || p.kernel == LB_KERNEL_STAGED) {
+        if (p.kernel == LB_KERNEL_STAGED && !staged_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
         int rc = build_tiles(s, p.tile_x, p.tile_y, p.tile_z);
         if (rc) return rc;
     } else if (p.kernel != LB_KERNEL_SPLIT) {
@@ -684,7 +691,11 @@ int lb_tune(lb_sim *s, int steps, lb_plan *best) {
     if (!s || steps < 1) return LB_EINVAL;
     std::vector<lb_plan> cands;
     cands.push_back(lb_plan{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0});
-    for (const auto &t : fused_tile_candidates(s->hdesc)) cands.push_back(lb_plan{LB_KERNEL_FUSED, t[0], t[1], t[2], 0, 0});
+    for (const auto &t : fused_tile_candidates(s->hdesc)) {
+        cands.push_back(lb_plan{LB_KERNEL_FUSED, t[0], t[1], t[2], 0, 0});
+        if (s->storage == LB_FP32 && staged_tile_ok(t[0], t[1]))
+            cands.push_back(lb_plan{LB_KERNEL_STAGED, t[0], t[1], t[2], 0, 0});
+    }
     const int64_t P = graph_period(s);
     const int gsteps = (int)(ceil_div(std::max<int64_t>(steps, 8), P) * P);
     hipEvent_t e0, e1;

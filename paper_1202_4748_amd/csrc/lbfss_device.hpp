@@ -178,27 +178,30 @@ __device__ __forceinline__ float collide_site(const RepDesc &d, float (&r)[Q], f
     float p13 = g * m13, p14 = g * m14, p15 = g * m15;
     float p16 = g * m16, p17 = g * m17, p18 = g * m18;
 
-    // thermal noise: sigma_a g_{a-4}, sigma_a = noise_amp sqrt(rho) sqrt(N_a)
+    // thermal noise: sigma_a g_{a-4}, sigma_a = noise_amp sqrt(rho) sqrt(N_a);
+    // generated and applied four normals (one Philox call) at a time
     {
-        float n[16];
-        noise(n);
         const float amp = d.noise_amp * __builtin_amdgcn_sqrtf(fmaxf(rho, 0.0f));
-        // sqrt(N_a) for a = 4..18
-        p4 += amp * 0.81649658092772603f * n[0];   // N = 2/3
-        p5 += amp * 1.1547005383792515f * n[1];    // 4/3
-        p6 += amp * 0.66666666666666667f * n[2];   // 4/9
-        p7 += amp * 0.33333333333333333f * n[3];   // 1/9
-        p8 += amp * 0.33333333333333333f * n[4];
-        p9 += amp * 0.33333333333333333f * n[5];
-        p10 += amp * 0.81649658092772603f * n[6];  // 2/3
-        p11 += amp * 0.81649658092772603f * n[7];
-        p12 += amp * 0.81649658092772603f * n[8];
-        p13 += amp * 0.47140452079103169f * n[9];  // 2/9
-        p14 += amp * 0.47140452079103169f * n[10];
-        p15 += amp * 0.47140452079103169f * n[11];
-        p16 += amp * 1.4142135623730951f * n[12];  // 2
-        p17 += amp * 1.1547005383792515f * n[13];  // 4/3
-        p18 += amp * 0.66666666666666667f * n[14]; // 4/9
+        float n[4];
+        noise(0, n);  // normals 0..3 -> moments 4..7
+        p4 += amp * 0.81649658092772603f * n[0];   // sqrt(N_4),  N = 2/3
+        p5 += amp * 1.1547005383792515f * n[1];    // N = 4/3
+        p6 += amp * 0.66666666666666667f * n[2];   // N = 4/9
+        p7 += amp * 0.33333333333333333f * n[3];   // N = 1/9
+        noise(1, n);  // normals 4..7 -> moments 8..11
+        p8 += amp * 0.33333333333333333f * n[0];
+        p9 += amp * 0.33333333333333333f * n[1];
+        p10 += amp * 0.81649658092772603f * n[2];  // N = 2/3
+        p11 += amp * 0.81649658092772603f * n[3];
+        noise(2, n);  // normals 8..11 -> moments 12..15
+        p12 += amp * 0.81649658092772603f * n[0];
+        p13 += amp * 0.47140452079103169f * n[1];  // N = 2/9
+        p14 += amp * 0.47140452079103169f * n[2];
+        p15 += amp * 0.47140452079103169f * n[3];
+        noise(3, n);  // normals 12..14 -> moments 16..18 (normal 15 unused)
+        p16 += amp * 1.4142135623730951f * n[0];   // N = 2
+        p17 += amp * 1.1547005383792515f * n[1];   // N = 4/3
+        p18 += amp * 0.66666666666666667f * n[2];  // N = 4/9
     }
 
     // back-transform: r*_i = sum_a e_a(c_i) m*_a / N_a
@@ -298,23 +301,21 @@ __device__ __forceinline__ void momentum_of(const float (&r)[Q], float &jx, floa
     jz = dZ + (dC - dD) + (dE - dF);
 }
 
-// The 16 collision normals of (site, step) from four Philox calls,
-// call j giving normals 4j .. 4j+3 (cos, sin of the word pairs (0,1), (2,3)).
+// The collision normals of (site, step): Philox call j (counter (site,
+// step_lo, j, step_hi)) gives normals 4j .. 4j+3 as the cos and sin of the
+// Box-Muller pairs of its word pairs (0, 1) and (2, 3).
 struct SiteNoise {
     uint32_t site, t_lo, t_hi, k0, k1;
-    __device__ __forceinline__ void operator()(float (&n)[16]) const {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const Words4 w = philox4x32_10(site, t_lo, (uint32_t)j, t_hi, k0, k1);
-            const float r0 = bm_radius(uniform01(w.v[0]));
-            const float a0 = uniform01(w.v[1]);
-            const float r1 = bm_radius(uniform01(w.v[2]));
-            const float a1 = uniform01(w.v[3]);
-            n[4 * j + 0] = r0 * cos_rev(a0);
-            n[4 * j + 1] = r0 * sin_rev(a0);
-            n[4 * j + 2] = r1 * cos_rev(a1);
-            n[4 * j + 3] = (j == 3) ? 0.0f : r1 * sin_rev(a1);  // normal 15 is unused
-        }
+    __device__ __forceinline__ void operator()(int j, float (&n)[4]) const {
+        const Words4 w = philox4x32_10(site, t_lo, (uint32_t)j, t_hi, k0, k1);
+        const float r0 = bm_radius(uniform01(w.v[0]));
+        const float a0 = uniform01(w.v[1]);
+        const float r1 = bm_radius(uniform01(w.v[2]));
+        const float a1 = uniform01(w.v[3]);
+        n[0] = r0 * cos_rev(a0);
+        n[1] = r0 * sin_rev(a0);
+        n[2] = r1 * cos_rev(a1);
+        n[3] = (j == 3) ? 0.0f : r1 * sin_rev(a1);  // normal 15 is unused
     }
 };
 

@@ -94,11 +94,10 @@ __device__ __forceinline__ int xcd_tile(int b, int nt) {
     return (b & 7) * per + (b >> 3);
 }
 
-template <typename T, int TX>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int TX, int TY, bool RING>
+__global__ void __launch_bounds__(TX * TY)
 k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const T *__restrict__ pop,
         T *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err) {
-    constexpr int TY = kBlock / TX;
     constexpr int EX = TX + 4, EP = EX * (TY + 4);
     constexpr int MX = TX + 2, MP = MX * (TY + 2);
     __shared__ float s_rho[5][EP];
@@ -124,13 +123,13 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
     const int r_in = (iy + 2) * EX + (ix + 2);  // LDS density index of the site
     const int m_in = (iy + 1) * MX + (ix + 1);  // LDS potential index of the site
 
-    // density halo: ring of the (nx+4) x (ny+4) extension, one site per thread
+    // density halo: ring of the (nx+4) x (ny+4) extension, at most two sites
+    // per thread; positions packed as (hy << 16) | hx, offsets formed per plane
+    constexpr int NT = TX * TY;
     const int ew = nx + 4;
     const int nhalo = 4 * (nx + ny) + 16;
-    const bool has_h = tid < nhalo;
-    int hx = 0, hy = 0;
-    if (has_h) {
-        int h = tid;
+    auto halo_pos = [&](int h) {
+        int hx, hy;
         if (h < 2 * ew) {
             hy = h / ew;
             hx = h - hy * ew;
@@ -144,10 +143,19 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
             const int k = h & 3;
             hx = k < 2 ? k : nx + k;
         }
-    }
-    PlaneOffs ho;
-    ho.set(wrap_near(tl.x0 - 2 + hx, L), wrap_near(tl.y0 - 2 + hy, L), L, sizeof(T));
-    const int r_h = hy * EX + hx;
+        return (uint32_t)((hy << 16) | hx);
+    };
+    const bool has_h = tid < nhalo, has_h2 = tid + NT < nhalo;
+    const uint32_t hp0 = has_h ? halo_pos(tid) : 0u;
+    const uint32_t hp1 = has_h2 ? halo_pos(tid + NT) : 0u;
+    auto halo_density = [&](const T *const (&qz)[Q], float *rs, uint32_t hp) {
+        const int hx = hp & 0xffff, hy = hp >> 16;
+        PlaneOffs ho;
+        ho.set(wrap_near(tl.x0 - 2 + hx, L), wrap_near(tl.y0 - 2 + hy, L), L, sizeof(T));
+        float h[Q];
+        pull_plane(qz, ho, h);
+        rs[hy * EX + hx] = drho_of(h);
+    };
 
     // potential halo: ring of the (nx+2) x (ny+2) extension
     const int mw = nx + 2;
@@ -188,14 +196,17 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
             }
             float *rs = s_rho[(p + 10) % 5];
             if (inner) {
-                pull_plane(qz, io, ld);
-                rs[r_in] = drho_of(ld);
+                if (RING) {
+                    pull_plane(qz, io, ld);
+                    rs[r_in] = drho_of(ld);
+                } else {
+                    float f[Q];
+                    pull_plane(qz, io, f);
+                    rs[r_in] = drho_of(f);
+                }
             }
-            if (has_h) {
-                float h[Q];
-                pull_plane(qz, ho, h);
-                rs[r_h] = drho_of(h);
-            }
+            if (has_h) halo_density(qz, rs, hp0);
+            if (has_h2) halo_density(qz, rs, hp1);
         }
         __syncthreads();
         // (b) chemical potential of plane p - 1
@@ -230,6 +241,18 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
                 Fy = gr.gy;
                 Fz = gr.gz;
             }
+            if (!RING) {  // pull plane z again (served by L2 / the last-level cache)
+                const int zc = wrap_near(z, L);
+                const uint32_t Zc = (uint32_t)zc * LL, Zm = (uint32_t)wrap_dec(zc, L) * LL,
+                               Zp = (uint32_t)wrap_inc(zc, L) * LL;
+                const T *qz[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int cz = cz_of(q);
+                    qz[q] = base + (size_t)q * N + (cz > 0 ? Zm : (cz < 0 ? Zp : Zc));
+                }
+                pull_plane(qz, io, cl);
+            }
             const uint32_t s = site_c + (uint32_t)z * LL;
             const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
             const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
@@ -250,9 +273,221 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
 }
 
 // ---------------------------------------------------------------------------
+// Staged variant (FP32 storage): the pulls of plane p + 1 (tile and halo) are
+// issued as asynchronous global-to-LDS loads as soon as plane p has been
+// consumed, so their latency hides behind the potential and collision
+// phases of plane p; no registers hold loads in flight.  The arithmetic is
+// the same function calls in the same order as k_fused.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(1))) const void *gptr_t;
+typedef __attribute__((address_space(3))) void *lptr_t;
+
+__device__ __forceinline__ uint32_t pull_off(int q, const PlaneOffs &o) {
+    switch (q) {
+    case 1: case 11: case 13: return o.xm;
+    case 2: case 12: case 14: return o.xp;
+    case 3: case 15: case 17: return o.ym;
+    case 4: case 16: case 18: return o.yp;
+    case 7: return o.mm;
+    case 8: return o.pp;
+    case 9: return o.mp;
+    case 10: return o.pm;
+    default: return o.c;
+    }
+}
+
+template <int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const float *__restrict__ pop,
+               float *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err) {
+    constexpr int NT = TX * TY;
+    constexpr int EX = TX + 4, EP = EX * (TY + 4);
+    constexpr int MX = TX + 2, MP = MX * (TY + 2);
+    constexpr int NH_MAX = 4 * (TX + TY) + 16;
+    static_assert(NH_MAX <= NT, "one halo site per thread");
+    constexpr int NHW = (NH_MAX + 63) / 64;  // waves that load halo sites
+    constexpr int NS = NT + NHW * 64;        // staging slots per population
+    __shared__ float s_stage[Q][NS];
+    __shared__ float s_rho[5][EP];
+    __shared__ float s_mu[4][MP];
+
+    const FusedTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const RepDesc &d = desc[tl.rep];
+    const int L = d.L;
+    const uint32_t N = (uint32_t)d.N, LL = (uint32_t)(L * L);
+    const float *base = pop + Q * d.site_off;
+    float *obase = pop_out + Q * d.site_off;
+    const uint64_t t = *step + (uint64_t)koff;
+    const bool force_on = !(d.flags & 1);
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ix = tid % TX, iy = tid / TX;
+    const int nx = tl.nx, ny = tl.ny;
+    const bool inner = ix < nx && iy < ny;
+    const int sx = tl.x0 + (inner ? ix : 0), sy = tl.y0 + (inner ? iy : 0);
+    const uint32_t site_c = (uint32_t)(sx + sy * L);
+    PlaneOffs io;
+    io.set(sx, sy, L, sizeof(float));
+    const int r_in = (iy + 2) * EX + (ix + 2);
+    const int m_in = (iy + 1) * MX + (ix + 1);
+
+    // density halo site of this thread (tid < nhalo); others load a valid dummy
+    const int ew = nx + 4;
+    const int nhalo = 4 * (nx + ny) + 16;
+    const bool has_h = tid < nhalo;
+    int hx = 0, hy = 0;
+    if (has_h) {
+        int h = tid;
+        if (h < 2 * ew) {
+            hy = h / ew;
+            hx = h - hy * ew;
+        } else if (h < 4 * ew) {
+            h -= 2 * ew;
+            hy = ny + 2 + h / ew;
+            hx = h - (h / ew) * ew;
+        } else {
+            h -= 4 * ew;
+            hy = 2 + (h >> 2);
+            const int k = h & 3;
+            hx = k < 2 ? k : nx + k;
+        }
+    }
+    PlaneOffs ho;
+    ho.set(wrap_near(tl.x0 - 2 + hx, L), wrap_near(tl.y0 - 2 + hy, L), L, sizeof(float));
+    const int r_h = hy * EX + hx;
+
+    // potential halo
+    const int mw = nx + 2;
+    const int nmhalo = 2 * (nx + ny) + 4;
+    const bool has_mh = tid < nmhalo;
+    int mhx = 0, mhy = 0;
+    if (has_mh) {
+        int h = tid;
+        if (h < mw) {
+            mhy = 0;
+            mhx = h;
+        } else if (h < 2 * mw) {
+            mhy = ny + 1;
+            mhx = h - mw;
+        } else {
+            h -= 2 * mw;
+            mhy = 1 + (h >> 1);
+            mhx = (h & 1) ? nx + 1 : 0;
+        }
+    }
+    const int m_h = mhy * MX + mhx;
+    const int r_mh = (mhy + 1) * EX + (mhx + 1);
+
+    // does this wave store populations (then 19 stores may be younger than
+    // the staged loads when it next waits for them)
+    const bool wave_stores = __builtin_amdgcn_readfirstlane((int)(__ballot(inner) != 0)) != 0;
+
+    auto issue = [&](int p) {
+        const int zc = wrap_near(p, L);
+        const uint32_t Zc = (uint32_t)zc * LL, Zm = (uint32_t)wrap_dec(zc, L) * LL,
+                       Zp = (uint32_t)wrap_inc(zc, L) * LL;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int cz = cz_of(q);
+            const char *bq = (const char *)(base + (size_t)q * N + (cz > 0 ? Zm : (cz < 0 ? Zp : Zc)));
+            __builtin_amdgcn_global_load_lds((gptr_t)(bq + pull_off(q, io)), (lptr_t)&s_stage[q][wave * 64], 4, 0, 0);
+            if (wave < NHW)
+                __builtin_amdgcn_global_load_lds((gptr_t)(bq + pull_off(q, ho)), (lptr_t)&s_stage[q][NT + wave * 64],
+                                                 4, 0, 0);
+        }
+    };
+
+    bool bad = false;
+    float A[Q], B[Q], C[Q];
+    bool stored_last = false;  // did the previous iteration issue stores (wave-uniform)
+
+    auto body = [&](int p, float(&ld)[Q], float(&cl)[Q]) {
+        // 1. staged pulls of plane p have landed (stores of the last collision,
+        //    if any, are the only younger memory operations)
+        if (stored_last) __builtin_amdgcn_s_waitcnt(0x4F73);  // vmcnt <= 19
+        else __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt == 0
+        __syncthreads();
+        {
+            float *rs = s_rho[(p + 10) % 5];
+            if (inner) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) ld[q] = s_stage[q][tid];
+                rs[r_in] = drho_of(ld);
+            }
+            if (has_h) {
+                float h[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) h[q] = s_stage[q][NT + tid];
+                rs[r_h] = drho_of(h);
+            }
+        }
+        __syncthreads();
+        // 2. prefetch plane p + 1
+        if (p + 1 <= tl.z0 + tl.nz + 1) issue(p + 1);
+        // 3. chemical potential of plane p - 1
+        if (p - 1 >= tl.z0 - 1) {
+            const float *r0 = s_rho[(p - 2 + 10) % 5], *r1 = s_rho[(p - 1 + 10) % 5], *r2 = s_rho[(p + 10) % 5];
+            float *ms = s_mu[(p - 1 + 8) & 3];
+            auto mu_at = [&](int ri) {
+                const float c = r1[ri];
+                return chem_potential(d, c, lap18(c, [&](int dx, int dy, int dz) {
+                                          const float *pl = dz < 0 ? r0 : (dz > 0 ? r2 : r1);
+                                          return pl[ri + dy * EX + dx];
+                                      }));
+            };
+            if (inner) ms[m_in] = mu_at(r_in);
+            if (has_mh) ms[m_h] = mu_at(r_mh);
+        }
+        __syncthreads();
+        // 4. collision of plane z = p - 2
+        stored_last = false;
+        if (p - 2 >= tl.z0) {
+            stored_last = wave_stores;
+            if (inner) {
+                const int z = p - 2;
+                float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+                if (force_on) {
+                    const float *rm = s_rho[(z - 1 + 10) % 5], *rc = s_rho[(z + 10) % 5],
+                                *rp = s_rho[(z + 1 + 10) % 5];
+                    const float *mm = s_mu[(z - 1 + 8) & 3], *mc = s_mu[(z + 8) & 3], *mp = s_mu[(z + 1 + 8) & 3];
+                    const float rho_x = d.rho_c + rc[r_in];
+                    const Grad18 gr = grad18([&](int dx, int dy, int dz) {
+                        const float *rr = dz < 0 ? rm : (dz > 0 ? rp : rc);
+                        const float *mu = dz < 0 ? mm : (dz > 0 ? mp : mc);
+                        return (1.0f / 3.0f) * rr[r_in + dy * EX + dx] - rho_x * mu[m_in + dy * MX + dx];
+                    });
+                    Fx = gr.gx;
+                    Fy = gr.gy;
+                    Fz = gr.gz;
+                }
+                const uint32_t s = site_c + (uint32_t)z * LL;
+                const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
+                const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
+                bad |= !(rho > 0.0f && rho < 1e30f);  // Sec. III B: rho must stay positive
+                float *oz = obase + (uint32_t)z * LL;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) stb(oz + (size_t)q * N, io.c, cl[q]);
+            }
+        }
+    };
+
+    const int p0 = tl.z0 - 2, pend = tl.z0 + tl.nz + 1;
+    issue(p0);
+    for (int p = p0; p <= pend; p += 3) {
+        body(p, A, B);
+        if (p + 1 <= pend) body(p + 1, B, C);
+        if (p + 2 <= pend) body(p + 2, C, A);
+    }
+    if (bad) *err = 1;
+}
+
+// ---------------------------------------------------------------------------
 // Host side: tile tables and launch.
 // ---------------------------------------------------------------------------
-inline bool fused_tile_ok(int tx, int ty) { return (tx == 16 && ty == 16) || (tx == 32 && ty == 8); }
+inline bool fused_tile_ok(int tx, int ty) {
+    return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8) || (tx == 64 && ty == 4);
+}
 
 inline int make_fused_tiles(const std::vector<RepDesc> &reps, int tx, int ty, int tz,
                             std::vector<FusedTile> &out) {
@@ -284,6 +519,7 @@ inline std::vector<std::array<int, 3>> fused_tile_candidates(const std::vector<R
     std::vector<std::array<int, 3>> c;
     for (int tz : {16, 32, 64})
         if (tz <= std::max(maxL, 16)) {
+            c.push_back({64, 4, tz});
             c.push_back({32, 8, tz});
             c.push_back({16, 16, tz});
         }
@@ -291,16 +527,47 @@ inline std::vector<std::array<int, 3>> fused_tile_candidates(const std::vector<R
     return c;
 }
 
+#ifndef LBFSS_FUSED_RING
+#define LBFSS_FUSED_RING 1
+#endif
+constexpr bool kFusedRing = LBFSS_FUSED_RING;
+
 template <typename T>
 void launch_fused(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const T *in, T *out,
                   const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream) {
-    (void)ty;
-    if (tx == 16)
-        hipLaunchKernelGGL((k_fused<T, 16>), dim3(n_tiles), dim3(kBlock), 0, stream, desc, tiles, in, out, step,
-                           koff, err);
+    const bool ring = kFusedRing;
+#define LBFSS_LAUNCH_FUSED(TX_, TY_)                                                                          \
+    do {                                                                                                     \
+        if (ring)                                                                                            \
+            hipLaunchKernelGGL((k_fused<T, TX_, TY_, true>), dim3(n_tiles), dim3(TX_ * TY_), 0, stream, desc, \
+                               tiles, in, out, step, koff, err);                                             \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_fused<T, TX_, TY_, false>), dim3(n_tiles), dim3(TX_ * TY_), 0, stream,      \
+                               desc, tiles, in, out, step, koff, err);                                       \
+    } while (0)
+    if (tx == 16 && ty == 16) LBFSS_LAUNCH_FUSED(16, 16);
+    else if (tx == 16 && ty == 8) LBFSS_LAUNCH_FUSED(16, 8);
+    else if (tx == 64 && ty == 4) LBFSS_LAUNCH_FUSED(64, 4);
+    else LBFSS_LAUNCH_FUSED(32, 8);
+#undef LBFSS_LAUNCH_FUSED
+}
+
+inline bool staged_tile_ok(int tx, int ty) {
+    return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8);
+}
+
+inline void launch_fused_staged(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const float *in,
+                                float *out, const uint64_t *step, int koff, int *err, int tx, int ty,
+                                hipStream_t stream) {
+    if (tx == 16 && ty == 16)
+        hipLaunchKernelGGL((k_fused_staged<16, 16>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in, out,
+                           step, koff, err);
+    else if (tx == 16 && ty == 8)
+        hipLaunchKernelGGL((k_fused_staged<16, 8>), dim3(n_tiles), dim3(128), 0, stream, desc, tiles, in, out,
+                           step, koff, err);
     else
-        hipLaunchKernelGGL((k_fused<T, 32>), dim3(n_tiles), dim3(kBlock), 0, stream, desc, tiles, in, out, step,
-                           koff, err);
+        hipLaunchKernelGGL((k_fused_staged<32, 8>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in, out,
+                           step, koff, err);
 }
 
 }  // namespace lbfss

@@ -71,7 +71,7 @@ def test_ragged_sizes(L, tile):
     say(f"ragged L={L} tile={tile}")
     prm = dict(M0, a=0.01, b=0.5, tau=0.8)
     sim = lbf.Sim(L, 7 + L, **prm)
-    sim.set_plan("fused", tile)
+    sim.set_plan("staged" if tile[0] * tile[1] != 256 or tile[0] < 64 else "fused", tile)
     orc = oracle.Sim(L, 7 + L, **prm)
     for t in range(10):
         sim.step(1)
@@ -132,7 +132,8 @@ def test_plans_bit_identical():
     say("plans L=24")
     states = []
     for kernel, tile, g in [("split", (0, 0, 0), 0), ("fused", (16, 16, 8), 0), ("fused", (32, 8, 24), 0),
-                            ("fused", (32, 8, 5), 6), ("split", (0, 0, 0), 4)]:
+                            ("fused", (32, 8, 5), 6), ("split", (0, 0, 0), 4), ("fused", (64, 4, 7), 0),
+                            ("staged", (32, 8, 9), 0), ("staged", (16, 16, 24), 0), ("staged", (16, 8, 5), 4)]:
         sim = lbf.Sim(L, 11, **M0)
         sim.set_plan(kernel, tile, g)
         sim.step(13)
