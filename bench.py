@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {0: "split", 1: "fused", 2: "staged"}
 BYTES_PER_SITE = {"fp32": 152, "fp16": 76}
 
 
@@ -36,19 +37,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+STEP_KERNEL_SOURCES = ("lbfss_device.hpp", "lbfss_step.hpp", "lbfss_fused.hpp")
+
+
 def kernel_source_hash():
+    """Hash of the sources the step kernels are built from (the traffic
+    counters are only valid for the kernel they were taken on)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1202_4748_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in STEP_KERNEL_SOURCES:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload, storage):
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+def read_traffic(kname, workload, storage):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary, or None if absent or taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_k_fused_{workload}_{storage}.md")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kname}_{workload}_{storage}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -72,6 +78,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only run warmup + timed steps (for profiler runs)")
+    ap.add_argument("--plan", default=None,
+                    help="fixed launch plan kernel:tx:ty:tz:graph_steps (kernel split|fused|staged)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -94,11 +104,21 @@ def main():
     wl.pop("storage", None)
     N = L ** 3
     log(f"[bench] {args.workload}: {L}^3, storage {args.storage}, sample every {args.sample_every}")
+    if args.calibrate_copy:
+        x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     sim = lbf.Sim(L, workloads.SEED, storage=args.storage, sample_every=args.sample_every, **wl)
+    if args.plan:
+        k, tx, ty, tz, g = args.plan.split(":")
+        sim.set_plan(k, (int(tx), int(ty), int(tz)), int(g))
+        log(f"[bench] plan {sim.plan()}")
+    elif not args.no_tune and not args.kernel_only:
+        sim.tune(steps=10)
+        log(f"[bench] tuned plan {sim.plan()}")
     plan = sim.plan()
-    if not args.no_tune and not args.kernel_only:
-        plan = sim.tune(steps=10)
-        log(f"[bench] tuned plan {plan}")
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -113,13 +133,12 @@ def main():
         print(json.dumps({"metric": "MLUPS", "value": mlups, "steps": args.steps}))
         return
     mom = sim.moments()
-    mass_drift = None
 
     # dominant kernel alone: same plan without sample steps, HIP events on its stream
     kplan = dict(plan)
     ksim = lbf.Sim(L, workloads.SEED, storage=args.storage, **wl)
-    ksim.set_plan("fused" if kplan["kernel"] == lbf.LB_KERNEL_FUSED else "split",
-                  (kplan["tile_x"], kplan["tile_y"], kplan["tile_z"]), max(kplan["graph_steps"], 20))
+    ksim.set_plan(KERNEL_NAMES[kplan["kernel"]], (kplan["tile_x"], kplan["tile_y"], kplan["tile_z"]),
+                  max(kplan["graph_steps"], 20))
     ksim.step(40)
     ksim.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -131,9 +150,9 @@ def main():
     ms_per_launch = e0.elapsed_time(e1) / nk
     algo_bytes = BYTES_PER_SITE[args.storage] * N
     achieved = algo_bytes / (ms_per_launch * 1e-3) / 1e9
-    kname = "k_fused" if kplan["kernel"] == lbf.LB_KERNEL_FUSED else "k_collide"
+    kname = {0: "k_collide", 1: "k_fused", 2: "k_fused_staged"}[kplan["kernel"]]
     log(f"[bench] {kname}: {ms_per_launch * 1e3:.1f} us per step, {achieved:.0f} GB/s algorithmic")
-    traffic = read_traffic(args.workload, args.storage)
+    traffic = read_traffic(kname, args.workload, args.storage)
     del ksim
 
     result = {
@@ -191,8 +210,8 @@ def batched_vs_plain(lbf, workloads, torch, steps=200):
     singles = []
     for L, sd, p in zip(Ls, seeds, prms):
         s = lbf.Sim(L, sd, **p)
-        s.set_plan("fused" if bplan["kernel"] == lbf.LB_KERNEL_FUSED else "split",
-                   (bplan["tile_x"], bplan["tile_y"], bplan["tile_z"]), bplan["graph_steps"])
+        s.set_plan(KERNEL_NAMES[bplan["kernel"]], (bplan["tile_x"], bplan["tile_y"], bplan["tile_z"]),
+                   bplan["graph_steps"])
         singles.append(s)
     for s in singles:  # same step count as the batch before its timed region
         s.step(t_before)
