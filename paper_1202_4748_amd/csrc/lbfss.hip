@@ -61,8 +61,8 @@ struct lb_sim {
     std::vector<SampDesc> hsd;
     SampDesc *d_sd = nullptr;
     int64_t *d_cum_rows = nullptr, *d_cum_cols = nullptr, *d_cum_bx = nullptr, *d_cum_by = nullptr,
-            *d_cum_bz = nullptr;
-    int64_t n_rows = 0, n_cols = 0, n_bx = 0, n_by = 0, n_bz = 0;
+            *d_cum_bz = nullptr, *d_cum_planes = nullptr, *d_cum_direct = nullptr, *d_cum_sk = nullptr;
+    int64_t n_rows = 0, n_cols = 0, n_bx = 0, n_by = 0, n_bz = 0, n_planes = 0, n_direct = 0, n_sk = 0;
     std::vector<int64_t *> d_cum_coarse;
     std::vector<int64_t> n_coarse;
     int max_nlev = 0;
@@ -194,7 +194,10 @@ void launch_totals(lb_sim *s, int cur) {
                        s->d_sd, s->d_cum_rows, s->nrep, s->total_sites, (const float *)s->d_snap, s->d_ws);
     hipLaunchKernelGGL(k_cols, dim3((unsigned)ceil_div(s->n_cols, kBlock)), dim3(kBlock), 0, s->stream,
                        s->d_sd, s->d_cum_cols, s->nrep, (const float *)s->d_snap, s->d_ws);
-    hipLaunchKernelGGL(k_globals, dim3(s->nrep), dim3(kBlock), 0, s->stream, s->d_sd, s->d_desc, s->d_ws);
+    hipLaunchKernelGGL(k_planes, dim3((unsigned)ceil_div(s->n_planes, kBlock)), dim3(kBlock), 0, s->stream,
+                       s->d_sd, s->d_cum_planes, s->nrep, s->d_ws);
+    hipLaunchKernelGGL(k_totals, dim3((unsigned)ceil_div(s->nrep, 64)), dim3(64), 0, s->stream, s->d_sd,
+                       s->d_desc, s->nrep, s->d_ws);
 }
 
 void enqueue_totals(lb_sim *s, int cur) {
@@ -204,6 +207,9 @@ void enqueue_totals(lb_sim *s, int cur) {
 
 void enqueue_sample(lb_sim *s, int cur, int koff) {
     enqueue_totals(s, cur);
+    if (s->n_direct > 0)
+        hipLaunchKernelGGL(k_box_direct, dim3((unsigned)ceil_div(s->n_direct, kBlock)), dim3(kBlock), 0,
+                           s->stream, s->d_sd, s->d_cum_direct, s->nrep, (const float *)s->d_snap, s->d_ws);
     if (s->n_bx > 0) {
         hipLaunchKernelGGL(k_box_x, dim3((unsigned)ceil_div(s->n_bx, kBlock)), dim3(kBlock), 0, s->stream,
                            s->d_sd, s->d_cum_bx, s->nrep, (const float *)s->d_snap, s->d_ws);
@@ -219,7 +225,10 @@ void enqueue_sample(lb_sim *s, int cur, int koff) {
     }
     if (s->n_chunks > 0)
         hipLaunchKernelGGL(k_level_partials, dim3(s->n_chunks), dim3(kBlock), 0, s->stream, s->d_sd, s->d_chunks,
-                           s->d_ws, s->d_parts);
+                           (const float *)s->d_snap, s->d_ws, s->d_parts);
+    if (s->n_sk > 0)
+        hipLaunchKernelGGL(k_structure_factor, dim3((unsigned)ceil_div(s->n_sk, kBlock)), dim3(kBlock), 0,
+                           s->stream, s->d_sd, s->d_cum_sk, s->nrep, (const double *)s->d_ws, s->d_acc);
     hipLaunchKernelGGL(k_finalize, dim3(s->nrep), dim3(kBlock), 0, s->stream, s->d_sd, s->d_ws,
                        (const double *)s->d_parts, s->d_acc, s->d_series, s->d_nsamp, (const uint64_t *)s->d_step,
                        koff);
@@ -271,9 +280,11 @@ int build_graph(lb_sim *s, int G) {
 }
 
 int build_sampling(lb_sim *s) {
-    int64_t ws_len = 0, acc_len = 0, ser_len = 0, parts_rows = 0;
+    int64_t ws_len = 0, acc_len = 0, ser_len = 0;
     std::vector<BoxChunk> chunks;
-    std::vector<int64_t> cum_rows{0}, cum_cols{0}, cum_bx{0}, cum_by{0}, cum_bz{0};
+    std::vector<int64_t> cum_rows{0}, cum_cols{0}, cum_bx{0}, cum_by{0}, cum_bz{0}, cum_planes{0}, cum_direct{0},
+        cum_sk{0};
+    std::vector<std::pair<int64_t, std::vector<double>>> twid;
     s->max_nlev = 0;
     for (int r = 0; r < s->nrep; ++r)
         s->max_nlev = std::max<int>(s->max_nlev, (int)block_levels(s->L[r], s->P[r].n_levels).size());
@@ -291,17 +302,44 @@ int build_sampling(lb_sim *s) {
         d.series_cap = s->P[r].series_capacity;
         d.rec_len = 5 + kMoments * d.nlev;
         d.site_off = s->hdesc[r].site_off;
+        // which level holds stored box sums, and how the finest ones are formed
+        d.base_lev = d.snap_lev = -1;
+        d.direct = 0;
+        if (d.nlev > 0) {
+            if (d.Lmin == 1) {
+                d.snap_lev = d.nlev - 1;           // one-site boxes: read the snapshot
+                d.base_lev = d.nlev - 2;           // two-site boxes summed from the snapshot
+                d.direct = 1;
+            } else {
+                d.base_lev = d.nlev - 1;
+                d.direct = d.Lmin <= 4 ? 1 : 0;    // larger boxes: separable x, y, z sums
+            }
+        }
         const int64_t LL = (int64_t)L * L;
         d.rows_off = ws_len; ws_len += 4 * LL;
         d.cols_off = ws_len; ws_len += LL;
-        d.planes_off = ws_len; ws_len += 3 * L;
-        d.a_off = ws_len; ws_len += 2 * LL * d.nb;
-        d.b_off = ws_len; ws_len += 2 * (int64_t)L * d.nb * d.nb;
+        d.planes_off = ws_len; ws_len += 6 * L;
+        d.twid_off = ws_len; ws_len += 2 * L;
+        {
+            std::vector<double> tw(2 * L);
+            for (int k = 0; k < L; ++k) {
+                tw[k] = std::cos(2.0 * M_PI * k / L);
+                tw[L + k] = std::sin(2.0 * M_PI * k / L);
+            }
+            twid.emplace_back(d.twid_off, std::move(tw));
+        }
+        const bool separable = d.nlev > 0 && !d.direct;
+        if (separable) {
+            d.a_off = ws_len; ws_len += 2 * LL * d.nb;
+            d.b_off = ws_len; ws_len += 2 * (int64_t)L * d.nb * d.nb;
+        }
         for (int l = 0; l < d.nlev; ++l) {
             const int64_t nbl = L / lev[l];
             d.lev_L[l] = lev[l];
-            d.lev_off[l] = ws_len;
-            ws_len += 2 * nbl * nbl * nbl;
+            if (l <= d.base_lev) {
+                d.lev_off[l] = ws_len;
+                ws_len += 2 * nbl * nbl * nbl;
+            }
             d.chunk_first[l] = (int64_t)chunks.size();
             const int64_t nboxes = nbl * nbl * nbl;
             int cnt = 0;
@@ -314,14 +352,20 @@ int build_sampling(lb_sim *s) {
         d.series_off = ser_len; ser_len += (int64_t)d.series_cap * d.rec_len;
         cum_rows.push_back(cum_rows.back() + LL);
         cum_cols.push_back(cum_cols.back() + LL);
-        // a lattice without block levels (odd L) has no box work
-        const bool boxes = d.nlev > 0;
-        cum_bx.push_back(cum_bx.back() + (boxes ? LL * d.nb : 0));
-        cum_by.push_back(cum_by.back() + (boxes ? (int64_t)L * d.nb * d.nb : 0));
-        cum_bz.push_back(cum_bz.back() + (boxes ? (int64_t)d.nb * d.nb * d.nb : 0));
+        cum_planes.push_back(cum_planes.back() + 6 * L);
+        cum_sk.push_back(cum_sk.back() + 3 * d.n_k);
+        int64_t ndirect = 0;
+        if (d.direct && d.base_lev >= 0) {
+            const int64_t nbl = L / lev[d.base_lev];
+            ndirect = nbl * nbl * nbl;
+        }
+        cum_direct.push_back(cum_direct.back() + ndirect);
+        cum_bx.push_back(cum_bx.back() + (separable ? LL * d.nb : 0));
+        cum_by.push_back(cum_by.back() + (separable ? (int64_t)L * d.nb * d.nb : 0));
+        cum_bz.push_back(cum_bz.back() + (separable ? (int64_t)d.nb * d.nb * d.nb : 0));
         for (int l = 0; l + 1 < s->max_nlev; ++l) {
             int64_t n = 0;
-            if (l + 1 < d.nlev) {
+            if (l < d.base_lev) {  // coarser than the stored base: from the next finer level
                 const int64_t nbl = L / lev[l];
                 n = nbl * nbl * nbl;
             }
@@ -329,9 +373,12 @@ int build_sampling(lb_sim *s) {
         }
         s->hsd.push_back(d);
     }
-    parts_rows = (int64_t)chunks.size();
+    const int64_t parts_rows = (int64_t)chunks.size();
     s->n_rows = cum_rows.back();
     s->n_cols = cum_cols.back();
+    s->n_planes = cum_planes.back();
+    s->n_sk = cum_sk.back();
+    s->n_direct = cum_direct.back();
     s->n_bx = cum_bx.back();
     s->n_by = cum_by.back();
     s->n_bz = cum_bz.back();
@@ -339,6 +386,9 @@ int build_sampling(lb_sim *s) {
     if ((rc = upload(s, &s->d_sd, s->hsd))) return rc;
     if ((rc = upload(s, &s->d_cum_rows, cum_rows))) return rc;
     if ((rc = upload(s, &s->d_cum_cols, cum_cols))) return rc;
+    if ((rc = upload(s, &s->d_cum_planes, cum_planes))) return rc;
+    if ((rc = upload(s, &s->d_cum_sk, cum_sk))) return rc;
+    if ((rc = upload(s, &s->d_cum_direct, cum_direct))) return rc;
     if ((rc = upload(s, &s->d_cum_bx, cum_bx))) return rc;
     if ((rc = upload(s, &s->d_cum_by, cum_by))) return rc;
     if ((rc = upload(s, &s->d_cum_bz, cum_bz))) return rc;
@@ -357,6 +407,9 @@ int build_sampling(lb_sim *s) {
     s->d_series = (double *)dev_alloc(s, sizeof(double) * std::max<int64_t>(ser_len, 1));
     s->d_nsamp = (int64_t *)dev_alloc(s, sizeof(int64_t) * s->nrep);
     if (!s->d_parts || !s->d_snap || !s->d_ws || !s->d_acc || !s->d_series || !s->d_nsamp) return LB_ENOMEM;
+    for (const auto &tw : twid)
+        HIPCHK(hipMemcpy(s->d_ws + tw.first, tw.second.data(), sizeof(double) * tw.second.size(),
+                         hipMemcpyHostToDevice));
     s->acc_len = acc_len;
     s->series_len = ser_len;
     HIPCHK(hipMemsetAsync(s->d_acc, 0, sizeof(double) * std::max<int64_t>(acc_len, 1), s->stream));

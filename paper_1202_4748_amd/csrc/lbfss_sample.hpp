@@ -20,10 +20,15 @@ constexpr int kMoments = 7;  // m, m^2, m^3, m^4, |m|, E, E^2
 struct SampDesc {
     int32_t L, Lmin, nlev, nb;   // nb = L / Lmin boxes per axis at the finest level
     int32_t n_k, series_cap, rec_len, pad;
+    int32_t base_lev;            // finest level whose box sums are stored (-1: none)
+    int32_t snap_lev;            // level of one-site boxes, read from the snapshot (-1: none)
+    int32_t direct;              // base level summed straight from the snapshot (else separably)
+    int32_t pad2;
+    int64_t twid_off;            // 2 * L doubles: cos, sin of 2 pi k / L
     int64_t site_off;            // first site (snapshot index) of the replica
     int64_t rows_off;            // 4 * L^2 doubles: row sums of drho, jx, jy, jz, [4][z][y]
     int64_t cols_off;            // L^2 doubles: column sums of drho over y, [z][x]
-    int64_t planes_off;          // 3 * L doubles: plane sums P_x, P_y, P_z of drho
+    int64_t planes_off;          // 6 * L doubles: plane sums P_x, P_y, P_z of drho, P_z of jx, jy, jz
     int64_t a_off;               // 2 * L * L * nb: [2][z][y][bx]
     int64_t b_off;               // 2 * L * nb * nb: [2][z][by][bx]
     int64_t lev_off[kMaxLevels]; // 2 * (L/Lb)^3 each: [2][bz][by][bx], level 0 = L/2
@@ -128,53 +133,104 @@ k_cols(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nre
     const int64_t li = g - cum[r];
     const int L = s.L;
     const int64_t z = li / L, x = li - z * L;
-    double acc = 0.0;
-    for (int y = 0; y < L; ++y) acc += (double)snap[s.site_off + x + L * (y + L * z)];
-    ws[s.cols_off + li] = acc;
+    const float *col = snap + s.site_off + x + (int64_t)L * L * z;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};  // fixed interleave: deterministic, four loads in flight
+    int y = 0;
+    for (; y + 3 < L; y += 4)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] += (double)col[(int64_t)(y + k) * L];
+    for (; y < L; ++y) a[0] += (double)col[(int64_t)y * L];
+    ws[s.cols_off + li] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
-// 4. Per replica (one workgroup each): plane sums, total mass and momentum,
-// and the mean density deviation dbar that defines phi.
+// 4. Plane sums: one thread per (replica, plane family, n) over six families
+// P_x, P_y, P_z of drho and P_z of jx, jy, jz; L terms each, fixed order.
 __global__ void __launch_bounds__(kBlock)
-k_globals(const SampDesc *__restrict__ sd, const RepDesc *__restrict__ desc, double *__restrict__ ws) {
-    __shared__ double sh[kBlock];
-    const int r = blockIdx.x;
+k_planes(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep, double *__restrict__ ws) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= cum[nrep]) return;
+    const int r = find_cum(cum, nrep, g);
     const SampDesc &s = sd[r];
     const int L = s.L;
+    const int64_t li = g - cum[r];
+    const int fam = (int)(li / L), n = (int)(li - (int64_t)fam * L);
     const int64_t LL = (int64_t)L * L;
-    const double *rows = ws + s.rows_off;
-    const double *cols = ws + s.cols_off;
-    double *planes = ws + s.planes_off;
-    for (int n = threadIdx.x; n < L; n += kBlock) {
-        double px = 0.0, py = 0.0, pz = 0.0;
-        for (int k = 0; k < L; ++k) {
-            px += cols[(int64_t)k * L + n];   // sum over z of column sums at x = n
-            py += rows[(int64_t)k * L + n];   // sum over z of row sums at y = n
-            pz += rows[(int64_t)n * L + k];   // sum over y of row sums at z = n
-        }
-        planes[n] = px;
-        planes[L + n] = py;
-        planes[2 * L + n] = pz;
+    const double *src;
+    int64_t stride;
+    if (fam == 0) {        // P_x(n) = sum_z cols[z][n]
+        src = ws + s.cols_off + n;
+        stride = L;
+    } else if (fam == 1) { // P_y(n) = sum_z rows[z][n]
+        src = ws + s.rows_off + n;
+        stride = L;
+    } else {               // P_z(n) of channel fam - 2 = sum_y rows[c][n][y]
+        src = ws + s.rows_off + (fam - 2) * LL + (int64_t)n * L;
+        stride = 1;
     }
-    // totals: each thread sums a fixed strided subset of rows, then a tree
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = threadIdx.x; i < LL; i += kBlock)
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 3 < L; k += 4)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) t[c] += rows[c * LL + i];
+        for (int u = 0; u < 4; ++u) a[u] += src[(k + u) * stride];
+    for (; k < L; ++k) a[0] += src[k * stride];
+    ws[s.planes_off + li] = (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// 5. Totals (one thread per replica): mass, momentum and the mean density
+// deviation dbar that defines phi.
+__global__ void k_totals(const SampDesc *__restrict__ sd, const RepDesc *__restrict__ desc, int nrep,
+                         double *__restrict__ ws) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
+    const SampDesc &s = sd[r];
+    const int L = s.L;
     double tot[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) tot[c] = block_sum(t[c], sh);
-    if (threadIdx.x == 0) {
-        const double N = (double)L * (double)L * (double)L;
-        const double rho_c = (double)desc[r].rho_c;
-        double *gl = ws + s.glob_off;
-        gl[0] = tot[0] / N;               // dbar
-        gl[1] = rho_c + tot[0] / N;       // rho0
-        gl[2] = rho_c * N + tot[0];       // mass
-        gl[3] = tot[1];
-        gl[4] = tot[2];
-        gl[5] = tot[3];
+    for (int c = 0; c < 4; ++c) {
+        const double *P = ws + s.planes_off + (int64_t)(2 + c) * L;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        int k = 0;
+        for (; k + 3 < L; k += 4)
+            for (int u = 0; u < 4; ++u) a[u] += P[k + u];
+        for (; k < L; ++k) a[0] += P[k];
+        tot[c] = (a[0] + a[1]) + (a[2] + a[3]);
     }
+    const double N = (double)L * (double)L * (double)L;
+    const double rho_c = (double)desc[r].rho_c;
+    double *gl = ws + s.glob_off;
+    gl[0] = tot[0] / N;
+    gl[1] = rho_c + tot[0] / N;
+    gl[2] = rho_c * N + tot[0];
+    gl[3] = tot[1];
+    gl[4] = tot[2];
+    gl[5] = tot[3];
+}
+
+// Base-level box sums straight from the snapshot: one thread per box of edge
+// Lb <= 4 (at most 64 sites, z then y then x).
+__global__ void __launch_bounds__(kBlock)
+k_box_direct(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep,
+             const float *__restrict__ snap, double *__restrict__ ws) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= cum[nrep]) return;
+    const int r = find_cum(cum, nrep, g);
+    const SampDesc &s = sd[r];
+    const int64_t li = g - cum[r];
+    const int L = s.L, Lb = s.lev_L[s.base_lev];
+    const int64_t nbl = L / Lb;
+    const int64_t bz = li / (nbl * nbl), rem = li - bz * nbl * nbl;
+    const int64_t by = rem / nbl, bx = rem - by * nbl;
+    const float *src = snap + s.site_off + bx * Lb + (int64_t)L * (by * Lb + (int64_t)L * bz * Lb);
+    double a1 = 0.0, a2 = 0.0;
+    for (int dz = 0; dz < Lb; ++dz)
+        for (int dy = 0; dy < Lb; ++dy)
+            for (int dx = 0; dx < Lb; ++dx) {
+                const double v = (double)src[dx + (int64_t)L * (dy + (int64_t)L * dz)];
+                a1 += v;
+                a2 += v * v;
+            }
+    const int64_t cnt = nbl * nbl * nbl;
+    ws[s.lev_off[s.base_lev] + li] = a1;
+    ws[s.lev_off[s.base_lev] + cnt + li] = a2;
 }
 
 // 5.-7. Box sums of drho and drho^2 at the finest level Lmin, separably:
@@ -280,7 +336,7 @@ constexpr int kChunkBoxes = kBlock * kBoxesPerThread;
 
 __global__ void __launch_bounds__(kBlock)
 k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ chunks,
-                 double *__restrict__ ws, double *__restrict__ parts) {
+                 const float *__restrict__ snap, double *__restrict__ ws, double *__restrict__ parts) {
     __shared__ double sh[kBlock];
     const BoxChunk c = chunks[blockIdx.x];
     const SampDesc &s = sd[c.rep];
@@ -290,13 +346,22 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
     const double n = (double)Lb * (double)Lb * (double)Lb;
     const int64_t nbl = s.L / Lb;
     const int64_t cnt = nbl * nbl * nbl;
+    const bool from_snap = c.lev == s.snap_lev;  // one-site boxes: the snapshot itself
     const double *b1 = ws + s.lev_off[c.lev];
     const double *b2 = b1 + cnt;
+    const float *sn = snap + s.site_off;
     double acc[kMoments] = {0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < kBoxesPerThread; ++k) {
         const int64_t i = (int64_t)k * kBlock + threadIdx.x;
         if (i >= c.count) break;
-        const double B1 = b1[c.first + i], B2 = b2[c.first + i];
+        double B1, B2;
+        if (from_snap) {
+            B1 = (double)sn[c.first + i];
+            B2 = B1 * B1;
+        } else {
+            B1 = b1[c.first + i];
+            B2 = b2[c.first + i];
+        }
         const double sphi = (B1 - n * dbar) * inv_rho0;
         const double sphi2 = (B2 - 2.0 * dbar * B1 + n * dbar * dbar) * inv_rho0 * inv_rho0;
         const double m = sphi / n, E = sphi2 / (2.0 * n);
@@ -314,6 +379,35 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
         const double v = block_sum(acc[q], sh);
         if (threadIdx.x == 0) parts[(int64_t)blockIdx.x * kMoments + q] = v;
     }
+}
+
+// Axis structure factor S_a(k_m) = N^-1 |sum_n P_a(n) e^{-i k_m n}|^2 of phi,
+// one thread per (replica, axis, m), twiddles from the replica's FP64 table.
+__global__ void __launch_bounds__(kBlock)
+k_structure_factor(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep,
+                   const double *__restrict__ ws, double *__restrict__ acc_all) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= cum[nrep]) return;
+    const int r = find_cum(cum, nrep, g);
+    const SampDesc &s = sd[r];
+    const int idx = (int)(g - cum[r]);
+    const int L = s.L;
+    const int a = idx / s.n_k, m = idx - a * s.n_k + 1;
+    const double *planes = ws + s.planes_off + (int64_t)a * L;
+    const double *cs = ws + s.twid_off, *sn = cs + L;
+    const double *gl = ws + s.glob_off;
+    const double rho0 = gl[1], off = (double)L * L * gl[0];  // plane sum of rho0 - rho_c
+    double re = 0.0, im = 0.0;
+    int k = 0;
+    for (int n = 0; n < L; ++n) {
+        const double p = (planes[n] - off) / rho0;
+        re += p * cs[k];
+        im -= p * sn[k];
+        k += m;
+        if (k >= L) k -= L;
+    }
+    const double Nsites = (double)L * L * L;
+    acc_all[s.acc_off + s.nlev * kMoments + idx] += (re * re + im * im) / Nsites;
 }
 
 // 10. Per replica (one workgroup each): reduce the chunks of every level,
@@ -340,24 +434,6 @@ k_finalize(const SampDesc *__restrict__ sd, double *__restrict__ ws, const doubl
                 acc[lev * kMoments + q] += v;
             }
         }
-    }
-    // axis structure factor S_a(k_m) = N^-1 |sum_n P_a(n) e^{-i k_m n}|^2 of phi
-    const int L = s.L;
-    const double *planes = ws + s.planes_off;
-    const double rho0 = gl[1], dbar = gl[0];
-    const double Nsites = (double)L * L * L;
-    const double off = (double)L * L * dbar;  // plane sum of rho0 - rho_c
-    for (int idx = threadIdx.x; idx < 3 * s.n_k; idx += kBlock) {
-        const int a = idx / s.n_k, m = idx - a * s.n_k + 1;
-        double re = 0.0, im = 0.0;
-        for (int n = 0; n < L; ++n) {
-            const double p = (planes[a * L + n] - off) / rho0;
-            double sn, cs;
-            sincospi(2.0 * (double)((int64_t)m * n % L) / (double)L, &sn, &cs);
-            re += p * cs;
-            im -= p * sn;
-        }
-        acc[s.nlev * kMoments + idx] += (re * re + im * im) / Nsites;
     }
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -91,6 +91,9 @@ def axis_structure_factor(S, tau, **kw):
                      for m in range(1, S // 2)])
 
 
+_SK_CACHE = {}
+
+
 def box_variance(S, L, tau, **kw):
     """<m_L^2> of the linearized model: the block average of edge L of the
     order parameter phi = drho / rho0 has variance
@@ -103,7 +106,7 @@ def box_variance(S, L, tau, **kw):
     n = np.arange(L)
     B1 = np.array([np.abs(np.sum(np.exp(1j * kk * n))) ** 2 for kk in ks])
     # S(k) on the full grid, using the cubic symmetry to avoid recomputation
-    cache = {}
+    cache = _SK_CACHE.setdefault((S, tau, tuple(sorted(kw.items()))), {})
     for ix in range(S):
         for iy in range(S):
             for iz in range(S):
