@@ -46,7 +46,8 @@ def test_accumulators_match_oracle(L, n_levels, every):
             assert abs(lv[k] - ref[k]) <= 2e-5 * scale + 1e-22, (lv["Lb"], k, lv[k], ref[k])
         # boxes tile the lattice: sum of box means of phi is 0 up to rounding
         assert abs(lv["m"]) < 1e-9
-    assert np.allclose(got["sk"], acc.sk, rtol=2e-5, atol=1e-16)
+    # per-mode errors scale with the typical plane-sum size (mean S), not with S(k_m)
+    assert np.max(np.abs(got["sk"] - acc.sk)) <= 2e-5 * np.mean(acc.sk)
     ser = got["series"]
     assert ser.shape[0] == acc.n_samples
     # total momentum sums N per-site values whose FP32 trajectory differs from
