@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {0: "split", 1: "fused", 2: "staged"}
+KERNEL_NAMES = {0: "split", 1: "fused", 2: "staged", 3: "rows"}
 BYTES_PER_SITE = {"fp32": 152, "fp16": 76}
 
 
@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only run warmup + timed steps (for profiler runs)")
     ap.add_argument("--plan", default=None,
-                    help="fixed launch plan kernel:tx:ty:tz:graph_steps (kernel split|fused|staged)")
+                    help="fixed launch plan kernel:tx:ty:tz:graph_steps (kernel split|fused|staged|rows)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -150,7 +150,7 @@ def main():
     ms_per_launch = e0.elapsed_time(e1) / nk
     algo_bytes = BYTES_PER_SITE[args.storage] * N
     achieved = algo_bytes / (ms_per_launch * 1e-3) / 1e9
-    kname = {0: "k_collide", 1: "k_fused", 2: "k_fused_staged"}[kplan["kernel"]]
+    kname = {0: "k_collide", 1: "k_fused", 2: "k_fused_staged", 3: "k_fused_staged"}[kplan["kernel"]]
     log(f"[bench] {kname}: {ms_per_launch * 1e3:.1f} us per step, {achieved:.0f} GB/s algorithmic")
     traffic = read_traffic(kname, args.workload, args.storage)
     del ksim

@@ -130,14 +130,16 @@ typedef struct {
 enum {
     LB_KERNEL_SPLIT = 0,  /* density pass, chemical-potential pass, collide pass */
     LB_KERNEL_FUSED = 1,  /* one z-marching pass, density halo in LDS, pulls in registers */
-    LB_KERNEL_STAGED = 2  /* as FUSED, the next plane's pulls staged asynchronously in LDS
+    LB_KERNEL_STAGED = 2, /* as FUSED, the next plane's pulls staged asynchronously in LDS
                            * (FP32 storage; FP16 handles run FUSED) */
+    LB_KERNEL_ROWS = 3    /* as STAGED, the staging copies the source rows of each population
+                           * with 16-byte loads; every L a multiple of 4 (else LB_EINVAL) */
 };
 
 typedef struct {
-    int32_t kernel;      /* LB_KERNEL_SPLIT, LB_KERNEL_FUSED or LB_KERNEL_STAGED */
+    int32_t kernel;      /* LB_KERNEL_SPLIT, _FUSED, _STAGED or _ROWS */
     int32_t tile_x;      /* fused: tile edge along x; (tile_x, tile_y) in {(32,8), (16,16),
-                          * (16,8), (64,4)}, (64,4) not staged; clamped to L */
+                          * (16,8), (64,4)}, (64,4) not staged or rows; clamped to L */
     int32_t tile_y;      /* fused: tile edge along y */
     int32_t tile_z;      /* fused: planes marched by one workgroup */
     int32_t graph_steps; /* > 0: capture this many steps (rounded up to even) in a

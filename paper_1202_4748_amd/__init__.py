@@ -19,7 +19,7 @@ Q = 19
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
 LB_FP32, LB_FP16 = 0, 1
 LB_FORCE_OFF = 1
-LB_KERNEL_SPLIT, LB_KERNEL_FUSED, LB_KERNEL_STAGED = 0, 1, 2
+LB_KERNEL_SPLIT, LB_KERNEL_FUSED, LB_KERNEL_STAGED, LB_KERNEL_ROWS = 0, 1, 2, 3
 LB_MAX_LEVELS = 16
 
 EXPORTS = ("lb_create", "lb_create_batch", "lb_step", "lb_sync", "lb_moments", "lb_fields",
@@ -263,7 +263,8 @@ class Sim:
         _check(lib().lb_reset_moments(self._h), "lb_reset_moments")
 
     def set_plan(self, kernel="fused", tile=(32, 8, 32), graph_steps=0):
-        k = {"split": LB_KERNEL_SPLIT, "fused": LB_KERNEL_FUSED, "staged": LB_KERNEL_STAGED}[kernel]
+        k = {"split": LB_KERNEL_SPLIT, "fused": LB_KERNEL_FUSED, "staged": LB_KERNEL_STAGED,
+             "rows": LB_KERNEL_ROWS}[kernel]
         p = Plan(k, tile[0], tile[1], tile[2], graph_steps, 0)
         _check(lib().lb_set_plan(self._h, ctypes.byref(p)), "lb_set_plan")
 

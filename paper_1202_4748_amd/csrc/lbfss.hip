@@ -87,6 +87,14 @@ struct lb_sim {
     int g_steps = 0;
 };
 
+// The rows staging copies 16-byte chunks that must not straddle the periodic
+// seam: every lattice edge a multiple of 4.
+static bool rows_ok(const lb_sim *s) {
+    for (const auto &d : s->hdesc)
+        if (d.L % 4) return false;
+    return true;
+}
+
 namespace {
 
 int hip_fail(hipError_t e) { return e == hipSuccess ? LB_OK : (e == hipErrorOutOfMemory ? LB_ENOMEM : LB_EDEVICE); }
@@ -159,12 +167,17 @@ template <typename T>
 void launch_step(lb_sim *s, int cur, int koff) {
     const T *in = (const T *)s->pop[cur];
     T *out = (T *)s->pop[cur ^ 1];
-    if (s->plan.kernel == LB_KERNEL_STAGED && s->n_tiles > 0 && std::is_same<T, float>::value) {
-        launch_fused_staged(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out, s->d_step, koff,
-                            s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream);
+    if ((s->plan.kernel == LB_KERNEL_STAGED || s->plan.kernel == LB_KERNEL_ROWS) && s->n_tiles > 0 &&
+        std::is_same<T, float>::value) {
+        if (s->plan.kernel == LB_KERNEL_ROWS)
+            launch_fused_staged<true>(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out, s->d_step,
+                                      koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream);
+        else
+            launch_fused_staged<false>(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out,
+                                       s->d_step, koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream);
         return;
     }
-    if ((s->plan.kernel == LB_KERNEL_FUSED || s->plan.kernel == LB_KERNEL_STAGED) && s->n_tiles > 0) {
+    if (s->plan.kernel != LB_KERNEL_SPLIT && s->n_tiles > 0) {
         launch_fused<T>(s->d_desc, s->d_tiles, s->n_tiles, in, out, s->d_step, koff, s->d_err,
                         s->plan.tile_x, s->plan.tile_y, s->stream);
         return;
@@ -505,9 +518,10 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
                            s->nrep, s->total_sites, (const float *)s->d_drho, (float *)s->pop[0]);
     if (hipGetLastError() != hipSuccess) return fail(LB_EDEVICE);
     if ((rc = build_sampling(s))) return fail(rc);
-    // default plan: the fused kernel when every replica supports its tiles
-    lb_plan def{LB_KERNEL_FUSED, 64, 8, 16, 0, 0};
+    // default plan: the fused kernel, with rows staging where it applies
+    lb_plan def{LB_KERNEL_FUSED, 32, 8, 16, 0, 0};
     default_fused_tile(s->hdesc, def.tile_x, def.tile_y, def.tile_z);
+    if (s->storage == LB_FP32 && rows_ok(s)) def.kernel = LB_KERNEL_ROWS;
     if (lb_set_plan(s, &def) != LB_OK) {
         lb_plan split{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0};
         if ((rc = lb_set_plan(s, &split))) return fail(rc);
@@ -720,8 +734,11 @@ int lb_set_plan(lb_sim *s, const lb_plan *plan) {
         const int64_t P = graph_period(s);
         p.graph_steps = (int)(ceil_div(p.graph_steps, P) * P);
     }
-    if (p.kernel == LB_KERNEL_FUSED || p.kernel == LB_KERNEL_STAGED) {
+    if (p.kernel == LB_KERNEL_FUSED || p.kernel == LB_KERNEL_STAGED || p.kernel == LB_KERNEL_ROWS) {
+        if (p.kernel == LB_KERNEL_FUSED && !fused_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
         if (p.kernel == LB_KERNEL_STAGED && !staged_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
+        if (p.kernel == LB_KERNEL_ROWS && !staged_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
+        if (p.kernel == LB_KERNEL_ROWS && !rows_ok(s)) return LB_EINVAL;
         int rc = build_tiles(s, p.tile_x, p.tile_y, p.tile_z);
         if (rc) return rc;
     } else if (p.kernel != LB_KERNEL_SPLIT) {
@@ -746,8 +763,10 @@ int lb_tune(lb_sim *s, int steps, lb_plan *best) {
     cands.push_back(lb_plan{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0});
     for (const auto &t : fused_tile_candidates(s->hdesc)) {
         cands.push_back(lb_plan{LB_KERNEL_FUSED, t[0], t[1], t[2], 0, 0});
-        if (s->storage == LB_FP32 && staged_tile_ok(t[0], t[1]))
+        if (s->storage == LB_FP32 && staged_tile_ok(t[0], t[1])) {
             cands.push_back(lb_plan{LB_KERNEL_STAGED, t[0], t[1], t[2], 0, 0});
+            if (rows_ok(s)) cands.push_back(lb_plan{LB_KERNEL_ROWS, t[0], t[1], t[2], 0, 0});
+        }
     }
     const int64_t P = graph_period(s);
     const int gsteps = (int)(ceil_div(std::max<int64_t>(steps, 8), P) * P);

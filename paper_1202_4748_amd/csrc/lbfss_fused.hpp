@@ -17,6 +17,7 @@
 // in-plane offsets of a thread are computed once.
 #pragma once
 
+#include <algorithm>
 #include <array>
 #include <vector>
 
@@ -296,20 +297,34 @@ __device__ __forceinline__ uint32_t pull_off(int q, const PlaneOffs &o) {
     }
 }
 
-template <int TX, int TY>
+//
+// ROWS selects how plane p + 1 is staged.  false: every thread loads the 19
+// pulled values of its tile site, and threads of the first waves those of one
+// halo site each (dword per lane, the slot of a value is its site).  true:
+// for each population the workgroup copies the unshifted source rectangle
+// that the pulls of the tile and its two-site halo read, TY + 4 rows of
+// TX + 8 columns starting at x0 - 4 (16-byte aligned when L is a multiple
+// of 4), with 16-byte loads spread over all waves; a pulled value is then the
+// rectangle entry at the site's row and at column ex + 2 - cx_q.  The rows
+// mode issues about a quarter of the load instructions for the same data.
+template <int TX, int TY, bool ROWS>
 __global__ void __launch_bounds__(TX * TY)
 k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const float *__restrict__ pop,
                float *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err) {
     constexpr int NT = TX * TY;
+    constexpr int NW = NT / 64;
     constexpr int EX = TX + 4, EP = EX * (TY + 4);
     constexpr int MX = TX + 2, MP = MX * (TY + 2);
     constexpr int NH_MAX = 4 * (TX + TY) + 16;
     static_assert(NH_MAX <= NT, "one halo site per thread");
     constexpr int NHW = (NH_MAX + 63) / 64;  // waves that load halo sites
-    constexpr int NS = NT + NHW * 64;        // staging slots per population
+    // rows mode: source rectangle of RW floats per row, CW 16-byte chunks
+    constexpr int RW = TX + 8, CW = RW / 4, NL = CW * (TY + 4), NM = (NL + 63) / 64;
+    constexpr int NS = ROWS ? 4 * NL : NT + NHW * 64;  // staging floats per population
+    // rings: densities of planes p - 3 .. p, potentials of p - 3 .. p - 1
     __shared__ float s_stage[Q][NS];
-    __shared__ float s_rho[5][EP];
-    __shared__ float s_mu[4][MP];
+    __shared__ float s_rho[4][EP];
+    __shared__ float s_mu[3][MP];
 
     const FusedTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const RepDesc &d = desc[tl.rep];
@@ -383,7 +398,26 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     // the staged loads when it next waits for them)
     const bool wave_stores = __builtin_amdgcn_readfirstlane((int)(__ballot(inner) != 0)) != 0;
 
-    auto issue = [&](int p) {
+    // rows mode: the chunks this lane copies, one per 64-lane slice m of the
+    // NL chunks of a population: byte offsets of its column and of its row
+    // for the three y shifts (cy = -1, 0, 1)
+    uint32_t r_col[NM], r_row[NM][3];
+    bool r_on[NM];
+    if (ROWS) {
+        const int lane = tid & 63;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int j = m * 64 + lane;
+            r_on[m] = j < NL;
+            const int ey = j / CW, k = j - (j / CW) * CW;
+            r_col[m] = (uint32_t)(((tl.x0 - 4 + 4 * k) % L + L) % L) * sizeof(float);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                r_row[m][c] = (uint32_t)(((tl.y0 - 2 + ey - (c - 1)) % L + L) % L) * (uint32_t)L * sizeof(float);
+        }
+    }
+
+    auto issue = [&](int p) __attribute__((always_inline)) {
         const int zc = wrap_near(p, L);
         const uint32_t Zc = (uint32_t)zc * LL, Zm = (uint32_t)wrap_dec(zc, L) * LL,
                        Zp = (uint32_t)wrap_inc(zc, L) * LL;
@@ -391,34 +425,47 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
         for (int q = 0; q < Q; ++q) {
             const int cz = cz_of(q);
             const char *bq = (const char *)(base + (size_t)q * N + (cz > 0 ? Zm : (cz < 0 ? Zp : Zc)));
-            __builtin_amdgcn_global_load_lds((gptr_t)(bq + pull_off(q, io)), (lptr_t)&s_stage[q][wave * 64], 4, 0, 0);
-            if (wave < NHW)
-                __builtin_amdgcn_global_load_lds((gptr_t)(bq + pull_off(q, ho)), (lptr_t)&s_stage[q][NT + wave * 64],
-                                                 4, 0, 0);
+            if (ROWS) {
+                if (q % NW != wave) continue;  // populations are dealt round-robin to the waves
+#pragma unroll
+                for (int m = 0; m < NM; ++m)
+                    if (r_on[m])
+                        __builtin_amdgcn_global_load_lds((gptr_t)(bq + r_row[m][cy_of(q) + 1] + r_col[m]),
+                                                         (lptr_t)&s_stage[q][m * 256], 16, 0, 0);
+            } else {
+                __builtin_amdgcn_global_load_lds((gptr_t)(bq + pull_off(q, io)), (lptr_t)&s_stage[q][wave * 64], 4,
+                                                 0, 0);
+                if (wave < NHW)
+                    __builtin_amdgcn_global_load_lds((gptr_t)(bq + pull_off(q, ho)),
+                                                     (lptr_t)&s_stage[q][NT + wave * 64], 4, 0, 0);
+            }
         }
     };
+    // LDS slot of the pulled value q of the tile site / the halo site
+    auto slot_in = [&](int q) { return ROWS ? (iy + 2) * RW + ix + 4 - cx_of(q) : tid; };
+    auto slot_h = [&](int q) { return ROWS ? hy * RW + hx + 2 - cx_of(q) : NT + tid; };
 
     bool bad = false;
     float A[Q], B[Q], C[Q];
     bool stored_last = false;  // did the previous iteration issue stores (wave-uniform)
 
-    auto body = [&](int p, float(&ld)[Q], float(&cl)[Q]) {
+    auto body = [&](int p, float(&ld)[Q], float(&cl)[Q]) __attribute__((always_inline)) {
         // 1. staged pulls of plane p have landed (stores of the last collision,
         //    if any, are the only younger memory operations)
         if (stored_last) __builtin_amdgcn_s_waitcnt(0x4F73);  // vmcnt <= 19
         else __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt == 0
         __syncthreads();
         {
-            float *rs = s_rho[(p + 10) % 5];
+            float *rs = s_rho[(p + 8) & 3];
             if (inner) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) ld[q] = s_stage[q][tid];
+                for (int q = 0; q < Q; ++q) ld[q] = s_stage[q][slot_in(q)];
                 rs[r_in] = drho_of(ld);
             }
             if (has_h) {
                 float h[Q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) h[q] = s_stage[q][NT + tid];
+                for (int q = 0; q < Q; ++q) h[q] = s_stage[q][slot_h(q)];
                 rs[r_h] = drho_of(h);
             }
         }
@@ -427,8 +474,8 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
         if (p + 1 <= tl.z0 + tl.nz + 1) issue(p + 1);
         // 3. chemical potential of plane p - 1
         if (p - 1 >= tl.z0 - 1) {
-            const float *r0 = s_rho[(p - 2 + 10) % 5], *r1 = s_rho[(p - 1 + 10) % 5], *r2 = s_rho[(p + 10) % 5];
-            float *ms = s_mu[(p - 1 + 8) & 3];
+            const float *r0 = s_rho[(p - 2 + 8) & 3], *r1 = s_rho[(p - 1 + 8) & 3], *r2 = s_rho[(p + 8) & 3];
+            float *ms = s_mu[(p - 1 + 9) % 3];
             auto mu_at = [&](int ri) {
                 const float c = r1[ri];
                 return chem_potential(d, c, lap18(c, [&](int dx, int dy, int dz) {
@@ -448,9 +495,9 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
                 const int z = p - 2;
                 float Fx = 0.f, Fy = 0.f, Fz = 0.f;
                 if (force_on) {
-                    const float *rm = s_rho[(z - 1 + 10) % 5], *rc = s_rho[(z + 10) % 5],
-                                *rp = s_rho[(z + 1 + 10) % 5];
-                    const float *mm = s_mu[(z - 1 + 8) & 3], *mc = s_mu[(z + 8) & 3], *mp = s_mu[(z + 1 + 8) & 3];
+                    const float *rm = s_rho[(z - 1 + 8) & 3], *rc = s_rho[(z + 8) & 3],
+                                *rp = s_rho[(z + 1 + 8) & 3];
+                    const float *mm = s_mu[(z - 1 + 9) % 3], *mc = s_mu[(z + 9) % 3], *mp = s_mu[(z + 1 + 9) % 3];
                     const float rho_x = d.rho_c + rc[r_in];
                     const Grad18 gr = grad18([&](int dx, int dy, int dz) {
                         const float *rr = dz < 0 ? rm : (dz > 0 ? rp : rc);
@@ -491,7 +538,7 @@ inline bool fused_tile_ok(int tx, int ty) {
 
 inline int make_fused_tiles(const std::vector<RepDesc> &reps, int tx, int ty, int tz,
                             std::vector<FusedTile> &out) {
-    if (!fused_tile_ok(tx, ty) || tz < 1 || tz > 1024) return -1;
+    if (tx < 1 || ty < 1 || tz < 1 || tz > 1024) return -1;
     out.clear();
     for (size_t r = 0; r < reps.size(); ++r) {
         const int L = reps[r].L;
@@ -510,14 +557,20 @@ inline void default_fused_tile(const std::vector<RepDesc> &reps, int &tx, int &t
     for (const auto &d : reps) maxL = std::max(maxL, d.L);
     tx = 32;
     ty = 8;
-    tz = maxL >= 128 ? 32 : std::min(maxL, 16);
+    // six z slabs per column on large lattices: 2 x 768 tiles at L = 256
+    // fill 256 CUs holding three workgroups each in two even rounds
+    tz = maxL >= 128 ? (maxL + 5) / 6 : std::min(maxL, 16);
 }
 
 inline std::vector<std::array<int, 3>> fused_tile_candidates(const std::vector<RepDesc> &reps) {
     int maxL = 0;
     for (const auto &d : reps) maxL = std::max(maxL, d.L);
     std::vector<std::array<int, 3>> c;
-    for (int tz : {16, 32, 64})
+    std::vector<int> tzs{16, 32, 64};
+    for (int n : {3, 6})
+        if ((maxL + n - 1) / n > 16 && std::find(tzs.begin(), tzs.end(), (maxL + n - 1) / n) == tzs.end())
+            tzs.push_back((maxL + n - 1) / n);
+    for (int tz : tzs)
         if (tz <= std::max(maxL, 16)) {
             c.push_back({64, 4, tz});
             c.push_back({32, 8, tz});
@@ -556,18 +609,19 @@ inline bool staged_tile_ok(int tx, int ty) {
     return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8);
 }
 
-inline void launch_fused_staged(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const float *in,
-                                float *out, const uint64_t *step, int koff, int *err, int tx, int ty,
-                                hipStream_t stream) {
+
+template <bool ROWS>
+void launch_fused_staged(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const float *in, float *out,
+                         const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream) {
     if (tx == 16 && ty == 16)
-        hipLaunchKernelGGL((k_fused_staged<16, 16>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in, out,
-                           step, koff, err);
+        hipLaunchKernelGGL((k_fused_staged<16, 16, ROWS>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
+                           out, step, koff, err);
     else if (tx == 16 && ty == 8)
-        hipLaunchKernelGGL((k_fused_staged<16, 8>), dim3(n_tiles), dim3(128), 0, stream, desc, tiles, in, out,
-                           step, koff, err);
+        hipLaunchKernelGGL((k_fused_staged<16, 8, ROWS>), dim3(n_tiles), dim3(128), 0, stream, desc, tiles, in,
+                           out, step, koff, err);
     else
-        hipLaunchKernelGGL((k_fused_staged<32, 8>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in, out,
-                           step, koff, err);
+        hipLaunchKernelGGL((k_fused_staged<32, 8, ROWS>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
+                           out, step, koff, err);
 }
 
 }  // namespace lbfss

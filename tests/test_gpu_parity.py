@@ -46,7 +46,7 @@ def test_initial_state():
     _compare(sim, orc, 1e-7, "t=0")
 
 
-@pytest.mark.parametrize("kernel", ["split", "fused"])
+@pytest.mark.parametrize("kernel", ["split", "fused", "rows"])
 def test_config0_100_steps(kernel):
     """16^3, a=0, b=0.1, kappa=0.1, kT=1e-4, tau=1: every step of 100."""
     lbf = require_gpu()
@@ -63,15 +63,19 @@ def test_config0_100_steps(kernel):
     say(f"  worst field error {worst:.2e}, deviation-relative {dev_rel_err(rho_g, orc.rho()):.2e}")
 
 
-@pytest.mark.parametrize("L,tile", [(4, (16, 16, 4)), (7, (32, 8, 3)), (12, (16, 16, 5)), (20, (16, 16, 16)),
-                                    (37, (32, 8, 16)), (40, (32, 8, 7))])
-def test_ragged_sizes(L, tile):
-    """Sizes not divisible by the tile (partial tiles, wrap-around halos)."""
+@pytest.mark.parametrize("L,kernel,tile", [(4, "rows", (16, 16, 4)), (7, "staged", (32, 8, 3)),
+                                           (12, "rows", (16, 16, 5)), (12, "staged", (16, 8, 5)),
+                                           (20, "rows", (16, 16, 16)), (37, "staged", (32, 8, 16)),
+                                           (40, "rows", (32, 8, 7)), (44, "rows", (16, 8, 9)),
+                                           (36, "fused", (64, 4, 5))])
+def test_ragged_sizes(L, kernel, tile):
+    """Sizes not divisible by the tile (partial tiles, wrap-around halos, the
+    source rows of the rows staging wrapping more than once on L = 4)."""
     lbf = require_gpu()
-    say(f"ragged L={L} tile={tile}")
+    say(f"ragged L={L} {kernel} tile={tile}")
     prm = dict(M0, a=0.01, b=0.5, tau=0.8)
     sim = lbf.Sim(L, 7 + L, **prm)
-    sim.set_plan("staged" if tile[0] * tile[1] != 256 or tile[0] < 64 else "fused", tile)
+    sim.set_plan(kernel, tile)
     orc = oracle.Sim(L, 7 + L, **prm)
     for t in range(10):
         sim.step(1)
@@ -83,11 +87,11 @@ def test_strong_nonequilibrium_state():
     """A far-from-equilibrium state (drho 0.05, u 0.03, random ghosts) through
     the import path, with a strong quartic term."""
     lbf = require_gpu()
-    L = 10
-    say("strong state L=10")
+    L = 12
+    say("strong state L=12")
     f0 = workloads.random_populations(L, 99, drho=0.05, u=0.03, neq=0.02)
     prm = dict(a=-0.05, b=2.0, kappa=0.2, rho_c=1.0, kT=1e-4, tau=0.7)
-    for kernel in ("split", "fused"):
+    for kernel in ("split", "fused", "rows"):
         sim = lbf.Sim(L, 5, **prm)
         sim.set_plan(kernel, (16, 16, 4))
         sim.set_populations(f0)
@@ -126,14 +130,16 @@ def test_fp16_storage():
 
 
 def test_plans_bit_identical():
-    """Split, fused with different tiles and graph replay give the same bits."""
+    """Split, fused, staged and rows with different tiles and graph replay give
+    the same bits."""
     lbf = require_gpu()
     L = 24
     say("plans L=24")
     states = []
     for kernel, tile, g in [("split", (0, 0, 0), 0), ("fused", (16, 16, 8), 0), ("fused", (32, 8, 24), 0),
                             ("fused", (32, 8, 5), 6), ("split", (0, 0, 0), 4), ("fused", (64, 4, 7), 0),
-                            ("staged", (32, 8, 9), 0), ("staged", (16, 16, 24), 0), ("staged", (16, 8, 5), 4)]:
+                            ("staged", (32, 8, 9), 0), ("staged", (16, 16, 24), 0), ("staged", (16, 8, 5), 4),
+                            ("rows", (32, 8, 9), 0), ("rows", (16, 16, 24), 6), ("rows", (16, 8, 5), 0)]:
         sim = lbf.Sim(L, 11, **M0)
         sim.set_plan(kernel, tile, g)
         sim.step(13)
@@ -193,3 +199,15 @@ def test_unstable_flag_is_sticky():
     assert e.value.code == lbf.LB_EUNSTABLE
     with pytest.raises(lbf.LBError):
         sim.sync()
+
+
+def test_rows_plan_needs_multiple_of_four():
+    """The rows staging copies 16-byte chunks, so a lattice edge that is not a
+    multiple of 4 is refused with LB_EINVAL and the plan stays as it was."""
+    lbf = require_gpu()
+    sim = lbf.Sim(10, 1, **M0)
+    before = sim.plan()
+    with pytest.raises(lbf.LBError) as e:
+        sim.set_plan("rows", (32, 8, 4))
+    assert e.value.code == lbf.LB_EINVAL
+    assert sim.plan() == before
