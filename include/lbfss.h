@@ -88,8 +88,12 @@ typedef struct {
     int32_t n_levels;  /* block edges L_b = L / 2^l, l = 1..n_levels while integer; 0 = all */
     int32_t flags;     /* LB_FORCE_OFF or 0 */
     int32_t series_capacity; /* per-sample records kept (ring buffer); 0 = none */
-    int32_t reserved;  /* must be 0 */
+    int32_t hist_bins; /* > 0: histogram every level's box values m over this many equal
+                        * bins of [-hist_range, hist_range) (<= LB_MAX_HIST_BINS); 0 = none */
+    double hist_range; /* half-width of the histogram, > 0 when hist_bins > 0 */
 } lb_params;
+
+#define LB_MAX_HIST_BINS 4096
 
 typedef struct {
     int32_t Lb;        /* box edge */
@@ -175,6 +179,35 @@ int lb_sync(lb_sim *s);
  * series_record doubles: step, mass, momentum x, y, z, then per level
  * (coarsest first) the box means of m, m^2, m^3, m^4, |m|, E, E^2. */
 int lb_moments(lb_sim *s, int replica, lb_moments_t *out, double *sk, double *series);
+
+/* Order-parameter distribution P_L(m) of every level (Sec. II C, Eq. (PL-def):
+ * the histogram of the box values m_L^(b) over all boxes of all samples).
+ * counts: caller-owned, n_levels * (hist_bins + 2) entries, levels in the
+ * order of lb_moments_t.level (coarsest first); per level the hist_bins bins
+ * (box value m in bin k = floor((m + h) * (hist_bins / (2 h))), h =
+ * hist_range), then the number of values below -h, then the number at or
+ * above h.  Counts are exact integers, so batch and plan never change them.
+ * Synchronises.  LB_ESTATE if the replica was created with hist_bins = 0. */
+int lb_histogram(lb_sim *sim, int replica, uint64_t *counts);
+
+typedef struct {
+    int32_t Lb;          /* box edge */
+    int32_t reserved;
+    double P0;           /* density P_L(0): the bin holding 0, or the mean of the two bins
+                          * meeting at 0; densities are count / (all counted values * width) */
+    double chi_center;   /* L_b^3 / (2 pi kT P0^2): Eq. (PL-highT) at m = 0 */
+    double m_max;        /* |centre| of the fullest bin (lowest on ties): M_L as the
+                          * position of the maximum of P_L (Sec. IV C) */
+    double P_max;        /* density of that bin */
+    double chi_peak;     /* L_b^3 / (8 pi kT P_max^2): Eq. (PL-lowT) at m = M_L (Sec. IV C) */
+    double chi_var;      /* L_b^3 (<m^2> - <m>^2) / kT: Eq. (chiL), from the moment sums */
+    double chi_var_low;  /* L_b^3 (<m^2> - <|m|>^2) / kT: Eq. (chiL-lowT) */
+} lb_hist_est;           /* a zero denominator (empty bin, kT = 0) gives +inf */
+
+/* Susceptibility estimates of every level of a replica from its histogram and
+ * moment sums; out: caller-owned, n_levels entries (coarsest first).
+ * Synchronises.  LB_ESTATE if hist_bins = 0 or no sample was taken. */
+int lb_hist_estimates(lb_sim *sim, int replica, lb_hist_est *out);
 
 /* Current fields of one replica copied to host memory owned by the caller
  * (synchronising); any pointer may be NULL.  rho: L^3 doubles, j: 3 L^3

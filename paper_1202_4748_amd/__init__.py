@@ -24,7 +24,8 @@ LB_MAX_LEVELS = 16
 
 EXPORTS = ("lb_create", "lb_create_batch", "lb_step", "lb_sync", "lb_moments", "lb_fields",
            "lb_set_populations", "lb_reset_moments", "lb_set_stream", "lb_set_allocator",
-           "lb_set_plan", "lb_get_plan", "lb_tune", "lb_info", "lb_destroy", "lb_strerror")
+           "lb_set_plan", "lb_get_plan", "lb_tune", "lb_info", "lb_destroy", "lb_strerror",
+           "lb_histogram", "lb_hist_estimates")
 
 
 class Params(ctypes.Structure):
@@ -33,7 +34,13 @@ class Params(ctypes.Structure):
                 ("init_sigma", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("sample_every", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("series_capacity", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("hist_bins", ctypes.c_int32), ("hist_range", ctypes.c_double)]
+
+
+class HistEst(ctypes.Structure):
+    _fields_ = [("Lb", ctypes.c_int32), ("reserved", ctypes.c_int32), ("P0", ctypes.c_double),
+                ("chi_center", ctypes.c_double), ("m_max", ctypes.c_double), ("P_max", ctypes.c_double),
+                ("chi_peak", ctypes.c_double), ("chi_var", ctypes.c_double), ("chi_var_low", ctypes.c_double)]
 
 
 class LevelSums(ctypes.Structure):
@@ -106,6 +113,8 @@ def lib():
     L.lb_info.argtypes = [vp, ctypes.POINTER(InfoT)]
     L.lb_destroy.argtypes = [vp]
     L.lb_destroy.restype = None
+    L.lb_histogram.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint64)]
+    L.lb_hist_estimates.argtypes = [vp, i32, ctypes.POINTER(HistEst)]
     L.lb_strerror.argtypes = [i32]
     L.lb_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -157,10 +166,11 @@ def _use_torch():
 
 
 def make_params(a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, init_sigma=1e-3,
-                storage="fp32", sample_every=0, n_levels=0, force_off=False, series_capacity=0):
+                storage="fp32", sample_every=0, n_levels=0, force_off=False, series_capacity=0,
+                hist_bins=0, hist_range=0.0):
     st = {"fp32": LB_FP32, "fp16": LB_FP16, LB_FP32: LB_FP32, LB_FP16: LB_FP16}[storage]
     return Params(a, b, kappa, rho_c, kT, tau, init_sigma, st, sample_every, n_levels,
-                  LB_FORCE_OFF if force_off else 0, series_capacity, 0)
+                  LB_FORCE_OFF if force_off else 0, series_capacity, int(hist_bins), float(hist_range))
 
 
 class Sim:
@@ -183,6 +193,7 @@ class Sim:
                    "lb_create")
             self._h = h
             self.Ls = [int(L)]
+            self._hb = [int(params.get("hist_bins", 0))]
         if self._torch:
             import torch
             cs = torch.cuda.current_stream().cuda_stream
@@ -199,7 +210,9 @@ class Sim:
         arrS = (ctypes.c_uint64 * n)(*[int(s) for s in seeds])
         h = ctypes.c_void_p()
         _check(L_.lb_create_batch(n, arrL, arrP, arrS, ctypes.byref(h)), "lb_create_batch")
-        return cls(_handle=h, _Ls=Ls)
+        sim = cls(_handle=h, _Ls=Ls)
+        sim._hb = [int(p.get("hist_bins", 0)) for p in params_list]
+        return sim
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -258,6 +271,25 @@ class Sim:
         return {"step": m.step, "n_samples": m.n_samples, "mass": m.mass,
                 "momentum": np.array(m.momentum[:]), "L": m.L, "levels": levels,
                 "sk": sk[:3 * nk].reshape(3, nk), "series": ser}
+
+    def histogram(self, replica=0):
+        """Counts [n_levels, hist_bins + 2] of the box order parameter per level
+        (coarsest first): the bins, then below -hist_range, then at or above."""
+        m = self.moments(replica)
+        nlev = len(m["levels"])
+        n = nlev * (self._hb[replica] + 2)
+        buf = np.zeros(max(n, 1), dtype=np.uint64)
+        _check(lib().lb_histogram(self._h, int(replica), buf.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+               "lb_histogram")
+        return buf[:n].reshape(nlev, -1)
+
+    def hist_estimates(self, replica=0):
+        """Per level (coarsest first): P0, chi_center, m_max, P_max, chi_peak,
+        chi_var, chi_var_low (see lb_hist_est in include/lbfss.h)."""
+        nlev = len(self.moments(replica)["levels"])
+        arr = (HistEst * max(nlev, 1))()
+        _check(lib().lb_hist_estimates(self._h, int(replica), arr), "lb_hist_estimates")
+        return [{k: getattr(arr[i], k) for k, _ in HistEst._fields_ if k != "reserved"} for i in range(nlev)]
 
     def reset_moments(self):
         _check(lib().lb_reset_moments(self._h), "lb_reset_moments")

@@ -74,7 +74,8 @@ struct lb_sim {
     double *d_acc = nullptr;
     double *d_series = nullptr;
     int64_t *d_nsamp = nullptr;
-    int64_t acc_len = 0, series_len = 0;
+    unsigned long long *d_hist = nullptr;
+    int64_t acc_len = 0, series_len = 0, hist_len = 0;
 
     // fused plan work table
     FusedTile *d_tiles = nullptr;
@@ -159,7 +160,9 @@ int check_params(int L, const lb_params *p) {
         return LB_EINVAL;
     if (p->storage != LB_FP32 && p->storage != LB_FP16) return LB_EINVAL;
     if ((p->flags & ~LB_FORCE_OFF) != 0) return LB_EINVAL;
-    if (p->sample_every < 0 || p->n_levels < 0 || p->series_capacity < 0 || p->reserved != 0) return LB_EINVAL;
+    if (p->sample_every < 0 || p->n_levels < 0 || p->series_capacity < 0) return LB_EINVAL;
+    if (p->hist_bins < 0 || p->hist_bins > LB_MAX_HIST_BINS) return LB_EINVAL;
+    if (p->hist_bins > 0 && !(p->hist_range > 0 && std::isfinite(p->hist_range))) return LB_EINVAL;
     return LB_OK;
 }
 
@@ -238,7 +241,7 @@ void enqueue_sample(lb_sim *s, int cur, int koff) {
     }
     if (s->n_chunks > 0)
         hipLaunchKernelGGL(k_level_partials, dim3(s->n_chunks), dim3(kBlock), 0, s->stream, s->d_sd, s->d_chunks,
-                           (const float *)s->d_snap, s->d_ws, s->d_parts);
+                           (const float *)s->d_snap, s->d_ws, s->d_parts, s->d_hist);
     if (s->n_sk > 0)
         hipLaunchKernelGGL(k_structure_factor, dim3((unsigned)ceil_div(s->n_sk, kBlock)), dim3(kBlock), 0,
                            s->stream, s->d_sd, s->d_cum_sk, s->nrep, (const double *)s->d_ws, s->d_acc);
@@ -293,7 +296,7 @@ int build_graph(lb_sim *s, int G) {
 }
 
 int build_sampling(lb_sim *s) {
-    int64_t ws_len = 0, acc_len = 0, ser_len = 0;
+    int64_t ws_len = 0, acc_len = 0, ser_len = 0, hist_len = 0;
     std::vector<BoxChunk> chunks;
     std::vector<int64_t> cum_rows{0}, cum_cols{0}, cum_bx{0}, cum_by{0}, cum_bz{0}, cum_planes{0}, cum_direct{0},
         cum_sk{0};
@@ -362,6 +365,13 @@ int build_sampling(lb_sim *s) {
         }
         d.glob_off = ws_len; ws_len += 8;
         d.acc_off = acc_len; acc_len += (int64_t)kMoments * d.nlev + 3 * d.n_k;
+        d.hist_bins = s->P[r].hist_bins;
+        if (d.hist_bins > 0) {
+            d.hist_h = s->P[r].hist_range;
+            d.hist_inv_w = (double)d.hist_bins / (2.0 * d.hist_h);
+            d.hist_off = hist_len;
+            hist_len += (int64_t)d.nlev * (d.hist_bins + 2);
+        }
         d.series_off = ser_len; ser_len += (int64_t)d.series_cap * d.rec_len;
         cum_rows.push_back(cum_rows.back() + LL);
         cum_cols.push_back(cum_cols.back() + LL);
@@ -419,11 +429,15 @@ int build_sampling(lb_sim *s) {
     s->d_acc = (double *)dev_alloc(s, sizeof(double) * std::max<int64_t>(acc_len, 1));
     s->d_series = (double *)dev_alloc(s, sizeof(double) * std::max<int64_t>(ser_len, 1));
     s->d_nsamp = (int64_t *)dev_alloc(s, sizeof(int64_t) * s->nrep);
-    if (!s->d_parts || !s->d_snap || !s->d_ws || !s->d_acc || !s->d_series || !s->d_nsamp) return LB_ENOMEM;
+    s->d_hist = (unsigned long long *)dev_alloc(s, sizeof(unsigned long long) * std::max<int64_t>(hist_len, 1));
+    if (!s->d_parts || !s->d_snap || !s->d_ws || !s->d_acc || !s->d_series || !s->d_nsamp || !s->d_hist)
+        return LB_ENOMEM;
     for (const auto &tw : twid)
         HIPCHK(hipMemcpy(s->d_ws + tw.first, tw.second.data(), sizeof(double) * tw.second.size(),
                          hipMemcpyHostToDevice));
     s->acc_len = acc_len;
+    s->hist_len = hist_len;
+    HIPCHK(hipMemsetAsync(s->d_hist, 0, sizeof(unsigned long long) * std::max<int64_t>(hist_len, 1), s->stream));
     s->series_len = ser_len;
     HIPCHK(hipMemsetAsync(s->d_acc, 0, sizeof(double) * std::max<int64_t>(acc_len, 1), s->stream));
     HIPCHK(hipMemsetAsync(s->d_series, 0, sizeof(double) * std::max<int64_t>(ser_len, 1), s->stream));
@@ -634,6 +648,63 @@ int lb_moments(lb_sim *s, int replica, lb_moments_t *out, double *sk, double *se
     return check_err(s);
 }
 
+int lb_histogram(lb_sim *s, int replica, uint64_t *counts) {
+    if (!s || !counts || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    const SampDesc &d = s->hsd[replica];
+    if (d.hist_bins <= 0) return LB_ESTATE;
+    const size_t n = (size_t)d.nlev * (d.hist_bins + 2);
+    if (n > 0)
+        HIPCHK(hipMemcpyAsync(counts, s->d_hist + d.hist_off, sizeof(uint64_t) * n, hipMemcpyDeviceToHost,
+                              s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return check_err(s);
+}
+
+// Estimates of Sec. II B-C and IV C from the counts and the moment sums; an
+// empty denominator gives +inf.
+int lb_hist_estimates(lb_sim *s, int replica, lb_hist_est *out) {
+    if (!s || !out || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    const SampDesc &d = s->hsd[replica];
+    if (d.hist_bins <= 0) return LB_ESTATE;
+    lb_moments_t mo;
+    int rc = lb_moments(s, replica, &mo, nullptr, nullptr);
+    if (rc) return rc;
+    if (mo.n_samples <= 0) return LB_ESTATE;
+    const int nb = d.hist_bins;
+    std::vector<uint64_t> counts((size_t)d.nlev * (nb + 2));
+    if ((rc = lb_histogram(s, replica, counts.data()))) return rc;
+    const double kT = s->P[replica].kT, h = d.hist_h, w = 2.0 * h / nb;
+    const double pi = 3.14159265358979323846;
+    auto ratio = [](double num, double den) { return den > 0 ? num / den : (double)INFINITY; };
+    for (int l = 0; l < d.nlev; ++l) {
+        const uint64_t *c = counts.data() + (size_t)l * (nb + 2);
+        double total = 0.0;
+        for (int k = 0; k < nb + 2; ++k) total += (double)c[k];
+        const double tw = total * w;
+        int kmax = 0;
+        for (int k = 1; k < nb; ++k)
+            if (c[k] > c[kmax]) kmax = k;
+        const double P0 = (nb % 2) ? (double)c[nb / 2] / tw
+                                   : 0.5 * ((double)c[nb / 2 - 1] / tw + (double)c[nb / 2] / tw);
+        const double Pmax = (double)c[kmax] / tw;
+        const lb_level_sums &ls = mo.level[l];
+        const double n = (double)ls.n_boxes * (double)mo.n_samples;
+        const double mean = ls.sum_m / n, mean2 = ls.sum_m2 / n, mabs = ls.sum_abs_m / n;
+        const double vol = std::pow((double)ls.Lb, 3.0);
+        lb_hist_est &e = out[l];
+        e.Lb = ls.Lb;
+        e.reserved = 0;
+        e.P0 = P0;
+        e.chi_center = ratio(vol, 2.0 * pi * kT * P0 * P0);
+        e.m_max = std::fabs(-h + (kmax + 0.5) * w);
+        e.P_max = Pmax;
+        e.chi_peak = ratio(vol, 8.0 * pi * kT * Pmax * Pmax);
+        e.chi_var = ratio(vol * (mean2 - mean * mean), kT);
+        e.chi_var_low = ratio(vol * (mean2 - mabs * mabs), kT);
+    }
+    return LB_OK;
+}
+
 int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f) {
     if (!s || replica < 0 || replica >= s->nrep) return LB_EINVAL;
     const RepDesc &d = s->hdesc[replica];
@@ -708,6 +779,7 @@ int lb_reset_moments(lb_sim *s) {
     HIPCHK(hipMemsetAsync(s->d_acc, 0, sizeof(double) * std::max<int64_t>(s->acc_len, 1), s->stream));
     HIPCHK(hipMemsetAsync(s->d_series, 0, sizeof(double) * std::max<int64_t>(s->series_len, 1), s->stream));
     HIPCHK(hipMemsetAsync(s->d_nsamp, 0, sizeof(int64_t) * s->nrep, s->stream));
+    HIPCHK(hipMemsetAsync(s->d_hist, 0, sizeof(unsigned long long) * std::max<int64_t>(s->hist_len, 1), s->stream));
     return LB_OK;
 }
 

@@ -16,6 +16,7 @@ namespace lbfss {
 
 constexpr int kMaxLevels = 16;
 constexpr int kMoments = 7;  // m, m^2, m^3, m^4, |m|, E, E^2
+constexpr int kMaxHistBins = 4096;
 
 struct SampDesc {
     int32_t L, Lmin, nlev, nb;   // nb = L / Lmin boxes per axis at the finest level
@@ -38,6 +39,10 @@ struct SampDesc {
     int64_t acc_off;             // accumulators: nlev * 7 level sums, then 3 * n_k S(k) sums
     int64_t series_off;          // series_cap * rec_len doubles
     int64_t glob_off;            // 6 doubles: dbar, rhobar, mass, px, py, pz of the last reduction
+    int32_t hist_bins;           // histogram bins per level (0: none)
+    int32_t pad3;
+    double hist_h, hist_inv_w;   // half-width h and bins / (2 h)
+    int64_t hist_off;            // nlev * (hist_bins + 2) counters (uint64)
 };
 
 // A chunk of consecutive boxes of one (replica, level) reduced by one
@@ -330,16 +335,26 @@ k_coarsen(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int 
     ws[s.lev_off[lev] + cnt + li] = a2;
 }
 
-// 9. Partial sums over a chunk of boxes of m, m^2, m^3, m^4, |m|, E, E^2.
+// 9. Partial sums over a chunk of boxes of m, m^2, m^3, m^4, |m|, E, E^2,
+// and the chunk's contribution to the level's histogram of m (Sec. II C,
+// Eq. (PL-def)): counted in LDS, then added to the device counters (integer
+// sums, so the order of the additions cannot change them).
 constexpr int kBoxesPerThread = 16;
 constexpr int kChunkBoxes = kBlock * kBoxesPerThread;
 
 __global__ void __launch_bounds__(kBlock)
 k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ chunks,
-                 const float *__restrict__ snap, double *__restrict__ ws, double *__restrict__ parts) {
+                 const float *__restrict__ snap, double *__restrict__ ws, double *__restrict__ parts,
+                 unsigned long long *__restrict__ hist) {
     __shared__ double sh[kBlock];
+    __shared__ unsigned int s_hist[kMaxHistBins + 2];
     const BoxChunk c = chunks[blockIdx.x];
     const SampDesc &s = sd[c.rep];
+    const int nbins = s.hist_bins;  // uniform over the workgroup
+    if (nbins > 0) {
+        for (int i = threadIdx.x; i < nbins + 2; i += kBlock) s_hist[i] = 0u;
+        __syncthreads();
+    }
     const double *gl = ws + s.glob_off;
     const double dbar = gl[0], inv_rho0 = 1.0 / gl[1];
     const int Lb = s.lev_L[c.lev];
@@ -373,6 +388,18 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
         acc[4] += fabs(m);
         acc[5] += E;
         acc[6] += E * E;
+        if (nbins > 0) {
+            const double kf = floor((m + s.hist_h) * s.hist_inv_w);
+            // in range: its bin; below -h (or not a number): nbins; at or above h: nbins + 1
+            const int idx = (kf >= 0.0 && kf < (double)nbins) ? (int)kf : (kf >= (double)nbins ? nbins + 1 : nbins);
+            atomicAdd(&s_hist[idx], 1u);
+        }
+    }
+    if (nbins > 0) {
+        __syncthreads();
+        unsigned long long *hl = hist + s.hist_off + (int64_t)c.lev * (nbins + 2);
+        for (int i = threadIdx.x; i < nbins + 2; i += kBlock)
+            if (s_hist[i]) atomicAdd(&hl[i], (unsigned long long)s_hist[i]);
     }
 #pragma unroll
     for (int q = 0; q < kMoments; ++q) {

@@ -46,7 +46,10 @@ def test_invalid_arguments_rejected_before_device(L):
                   (16, lbf.make_params(tau=0.5)), (16, lbf.make_params(kT=-1.0)),
                   (16, lbf.make_params(kappa=-0.1)), (16, lbf.make_params(b=-1.0)),
                   (16, lbf.make_params(rho_c=0.0)), (16, lbf.make_params(init_sigma=-1.0)),
-                  (16, lbf.make_params(sample_every=-1)), (16, lbf.make_params(n_levels=-2))]:
+                  (16, lbf.make_params(sample_every=-1)), (16, lbf.make_params(n_levels=-2)),
+                  (16, lbf.make_params(hist_bins=-1)), (16, lbf.make_params(hist_bins=4097, hist_range=1.0)),
+                  (16, lbf.make_params(hist_bins=10, hist_range=0.0)),
+                  (16, lbf.make_params(hist_bins=10, hist_range=float("inf")))]:
         assert L.lb_create(L_, ctypes.byref(p), 1, ctypes.byref(h)) == lbf.LB_EINVAL
     bad = lbf.make_params()
     bad.storage = 7
@@ -58,4 +61,6 @@ def test_invalid_arguments_rejected_before_device(L):
     assert L.lb_create_batch(2, Ls, P, S, ctypes.byref(h)) == lbf.LB_EINVAL
     assert L.lb_step(None, 1) == lbf.LB_EINVAL
     assert L.lb_sync(None) == lbf.LB_EINVAL
+    assert L.lb_histogram(None, 0, None) == lbf.LB_EINVAL
+    assert L.lb_hist_estimates(None, 0, None) == lbf.LB_EINVAL
     L.lb_destroy(None)
