@@ -210,9 +210,9 @@ void launch_totals(lb_sim *s, int cur) {
                        s->d_sd, s->d_cum_rows, s->nrep, s->total_sites, (const float *)s->d_snap, s->d_ws);
     hipLaunchKernelGGL(k_cols, dim3((unsigned)ceil_div(s->n_cols, kBlock)), dim3(kBlock), 0, s->stream,
                        s->d_sd, s->d_cum_cols, s->nrep, (const float *)s->d_snap, s->d_ws);
-    hipLaunchKernelGGL(k_planes, dim3((unsigned)ceil_div(s->n_planes, kBlock)), dim3(kBlock), 0, s->stream,
+    hipLaunchKernelGGL(k_planes, dim3((unsigned)ceil_div(s->n_planes, kBlock / 64)), dim3(kBlock), 0, s->stream,
                        s->d_sd, s->d_cum_planes, s->nrep, s->d_ws);
-    hipLaunchKernelGGL(k_totals, dim3((unsigned)ceil_div(s->nrep, 64)), dim3(64), 0, s->stream, s->d_sd,
+    hipLaunchKernelGGL(k_totals, dim3((unsigned)s->nrep), dim3(kBlock), 0, s->stream, s->d_sd,
                        s->d_desc, s->nrep, s->d_ws);
 }
 
@@ -243,11 +243,13 @@ void enqueue_sample(lb_sim *s, int cur, int koff) {
         hipLaunchKernelGGL(k_level_partials, dim3(s->n_chunks), dim3(kBlock), 0, s->stream, s->d_sd, s->d_chunks,
                            (const float *)s->d_snap, s->d_ws, s->d_parts, s->d_hist);
     if (s->n_sk > 0)
-        hipLaunchKernelGGL(k_structure_factor, dim3((unsigned)ceil_div(s->n_sk, kBlock)), dim3(kBlock), 0,
+        hipLaunchKernelGGL(k_structure_factor, dim3((unsigned)ceil_div(s->n_sk, kBlock / 64)), dim3(kBlock), 0,
                            s->stream, s->d_sd, s->d_cum_sk, s->nrep, (const double *)s->d_ws, s->d_acc);
-    hipLaunchKernelGGL(k_finalize, dim3(s->nrep), dim3(kBlock), 0, s->stream, s->d_sd, s->d_ws,
-                       (const double *)s->d_parts, s->d_acc, s->d_series, s->d_nsamp, (const uint64_t *)s->d_step,
-                       koff);
+    if (s->max_nlev > 0)
+        hipLaunchKernelGGL(k_level_reduce, dim3((unsigned)(s->nrep * s->max_nlev)), dim3(kBlock), 0, s->stream,
+                           s->d_sd, s->max_nlev, s->d_ws, (const double *)s->d_parts, s->d_acc);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)ceil_div(s->nrep, 64)), dim3(64), 0, s->stream, s->d_sd, s->nrep,
+                       (const double *)s->d_ws, s->d_series, s->d_nsamp, (const uint64_t *)s->d_step, koff);
 }
 
 bool sampling(const lb_sim *s) { return s->sample_every > 0; }
@@ -364,6 +366,7 @@ int build_sampling(lb_sim *s) {
             d.chunk_count[l] = cnt;
         }
         d.glob_off = ws_len; ws_len += 8;
+        d.levtot_off = ws_len; ws_len += (int64_t)kMoments * std::max(d.nlev, 1);
         d.acc_off = acc_len; acc_len += (int64_t)kMoments * d.nlev + 3 * d.n_k;
         d.hist_bins = s->P[r].hist_bins;
         if (d.hist_bins > 0) {

@@ -43,6 +43,7 @@ struct SampDesc {
     int32_t pad3;
     double hist_h, hist_inv_w;   // half-width h and bins / (2 h)
     int64_t hist_off;            // nlev * (hist_bins + 2) counters (uint64)
+    int64_t levtot_off;          // nlev * 7 doubles: this sample's level sums
 };
 
 // A chunk of consecutive boxes of one (replica, level) reduced by one
@@ -75,6 +76,13 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     const double out = sh[0];
     __syncthreads();
     return out;
+}
+
+// Deterministic FP64 sum over one 64-lane wave (fixed butterfly).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
 }
 
 // 1. Snapshot of drho and j at every site (pulled populations), FP32.
@@ -148,12 +156,14 @@ k_cols(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nre
     ws[s.cols_off + li] = (a[0] + a[1]) + (a[2] + a[3]);
 }
 
-// 4. Plane sums: one thread per (replica, plane family, n) over six families
-// P_x, P_y, P_z of drho and P_z of jx, jy, jz; L terms each, fixed order.
+// 4. Plane sums: one 64-lane wave per (replica, plane family, n) over six
+// families P_x, P_y, P_z of drho and P_z of jx, jy, jz; lane l adds the
+// terms l, l + 64, ... in order, then a fixed butterfly.
 __global__ void __launch_bounds__(kBlock)
 k_planes(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep, double *__restrict__ ws) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= cum[nrep]) return;
+    const int64_t g = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= cum[nrep]) return;  // whole wave leaves together
     const int r = find_cum(cum, nrep, g);
     const SampDesc &s = sd[r];
     const int L = s.L;
@@ -172,42 +182,38 @@ k_planes(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int n
         src = ws + s.rows_off + (fam - 2) * LL + (int64_t)n * L;
         stride = 1;
     }
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    int k = 0;
-    for (; k + 3 < L; k += 4)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] += src[(k + u) * stride];
-    for (; k < L; ++k) a[0] += src[k * stride];
-    ws[s.planes_off + li] = (a[0] + a[1]) + (a[2] + a[3]);
+    double a = 0.0;
+    for (int k = lane; k < L; k += 64) a += src[k * stride];
+    a = wave_sum(a);
+    if (lane == 0) ws[s.planes_off + li] = a;
 }
 
-// 5. Totals (one thread per replica): mass, momentum and the mean density
+// 5. Totals (one workgroup per replica): mass, momentum and the mean density
 // deviation dbar that defines phi.
-__global__ void k_totals(const SampDesc *__restrict__ sd, const RepDesc *__restrict__ desc, int nrep,
-                         double *__restrict__ ws) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrep) return;
+__global__ void __launch_bounds__(kBlock)
+k_totals(const SampDesc *__restrict__ sd, const RepDesc *__restrict__ desc, int nrep, double *__restrict__ ws) {
+    __shared__ double sh[kBlock];
+    const int r = blockIdx.x;
     const SampDesc &s = sd[r];
     const int L = s.L;
     double tot[4];
     for (int c = 0; c < 4; ++c) {
         const double *P = ws + s.planes_off + (int64_t)(2 + c) * L;
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        int k = 0;
-        for (; k + 3 < L; k += 4)
-            for (int u = 0; u < 4; ++u) a[u] += P[k + u];
-        for (; k < L; ++k) a[0] += P[k];
-        tot[c] = (a[0] + a[1]) + (a[2] + a[3]);
+        double a = 0.0;
+        for (int k = threadIdx.x; k < L; k += kBlock) a += P[k];
+        tot[c] = block_sum(a, sh);
     }
-    const double N = (double)L * (double)L * (double)L;
-    const double rho_c = (double)desc[r].rho_c;
-    double *gl = ws + s.glob_off;
-    gl[0] = tot[0] / N;
-    gl[1] = rho_c + tot[0] / N;
-    gl[2] = rho_c * N + tot[0];
-    gl[3] = tot[1];
-    gl[4] = tot[2];
-    gl[5] = tot[3];
+    if (threadIdx.x == 0) {
+        const double N = (double)L * (double)L * (double)L;
+        const double rho_c = (double)desc[r].rho_c;
+        double *gl = ws + s.glob_off;
+        gl[0] = tot[0] / N;
+        gl[1] = rho_c + tot[0] / N;
+        gl[2] = rho_c * N + tot[0];
+        gl[3] = tot[1];
+        gl[4] = tot[2];
+        gl[5] = tot[3];
+    }
 }
 
 // Base-level box sums straight from the snapshot: one thread per box of edge
@@ -409,12 +415,14 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
 }
 
 // Axis structure factor S_a(k_m) = N^-1 |sum_n P_a(n) e^{-i k_m n}|^2 of phi,
-// one thread per (replica, axis, m), twiddles from the replica's FP64 table.
+// one 64-lane wave per (replica, axis, m), twiddles from the replica's FP64
+// table (index m n mod L); lanes take n = l, l + 64, ..., then a butterfly.
 __global__ void __launch_bounds__(kBlock)
 k_structure_factor(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep,
                    const double *__restrict__ ws, double *__restrict__ acc_all) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= cum[nrep]) return;
+    const int64_t g = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= cum[nrep]) return;  // whole wave leaves together
     const int r = find_cum(cum, nrep, g);
     const SampDesc &s = sd[r];
     const int idx = (int)(g - cum[r]);
@@ -425,62 +433,67 @@ k_structure_factor(const SampDesc *__restrict__ sd, const int64_t *__restrict__ 
     const double *gl = ws + s.glob_off;
     const double rho0 = gl[1], off = (double)L * L * gl[0];  // plane sum of rho0 - rho_c
     double re = 0.0, im = 0.0;
-    int k = 0;
-    for (int n = 0; n < L; ++n) {
+    for (int n = lane; n < L; n += 64) {
         const double p = (planes[n] - off) / rho0;
+        const int k = (int)(((int64_t)m * n) % L);
         re += p * cs[k];
         im -= p * sn[k];
-        k += m;
-        if (k >= L) k -= L;
     }
-    const double Nsites = (double)L * L * L;
-    acc_all[s.acc_off + s.nlev * kMoments + idx] += (re * re + im * im) / Nsites;
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+        const double Nsites = (double)L * L * L;
+        acc_all[s.acc_off + s.nlev * kMoments + idx] += (re * re + im * im) / Nsites;
+    }
 }
 
-// 10. Per replica (one workgroup each): reduce the chunks of every level,
-// add to the accumulators, add the axis structure factor, append a series
-// record and count the sample.
+// 10. One workgroup per (replica, level): reduce the level's chunk partial
+// sums in a fixed order, add them to the accumulators and keep this
+// sample's level sums for the series record.
 __global__ void __launch_bounds__(kBlock)
-k_finalize(const SampDesc *__restrict__ sd, double *__restrict__ ws, const double *__restrict__ parts,
-           double *__restrict__ acc_all, double *__restrict__ series_all, int64_t *__restrict__ nsamp,
-           const uint64_t *__restrict__ step, int koff) {
+k_level_reduce(const SampDesc *__restrict__ sd, int max_nlev, double *__restrict__ ws,
+               const double *__restrict__ parts, double *__restrict__ acc_all) {
     __shared__ double sh[kBlock];
-    __shared__ double lev_tot[kMaxLevels * kMoments];
-    const int r = blockIdx.x;
+    const int r = blockIdx.x / max_nlev, lev = blockIdx.x - r * max_nlev;
+    const SampDesc &s = sd[r];
+    if (lev >= s.nlev) return;  // whole workgroup
+    double *acc = acc_all + s.acc_off;
+    for (int q = 0; q < kMoments; ++q) {
+        double v = 0.0;
+        for (int64_t k = threadIdx.x; k < s.chunk_count[lev]; k += kBlock)
+            v += parts[(s.chunk_first[lev] + k) * kMoments + q];
+        v = block_sum(v, sh);
+        if (threadIdx.x == 0) {
+            ws[s.levtot_off + lev * kMoments + q] = v;
+            acc[lev * kMoments + q] += v;
+        }
+    }
+}
+
+// 11. Per replica (one thread each): append a series record, count the sample.
+__global__ void k_finalize(const SampDesc *__restrict__ sd, int nrep, const double *__restrict__ ws,
+                           double *__restrict__ series_all, int64_t *__restrict__ nsamp,
+                           const uint64_t *__restrict__ step, int koff) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrep) return;
     const SampDesc &s = sd[r];
     const double *gl = ws + s.glob_off;
-    double *acc = acc_all + s.acc_off;
-    for (int lev = 0; lev < s.nlev; ++lev) {
-        for (int q = 0; q < kMoments; ++q) {
-            double v = 0.0;
-            for (int64_t k = threadIdx.x; k < s.chunk_count[lev]; k += kBlock)
-                v += parts[(s.chunk_first[lev] + k) * kMoments + q];
-            v = block_sum(v, sh);
-            if (threadIdx.x == 0) {
-                lev_tot[lev * kMoments + q] = v;
-                acc[lev * kMoments + q] += v;
-            }
+    const double *lt = ws + s.levtot_off;
+    const int64_t k = nsamp[r];
+    if (s.series_cap > 0) {
+        double *rec = series_all + s.series_off + (k % s.series_cap) * s.rec_len;
+        rec[0] = (double)(*step + (uint64_t)koff);
+        rec[1] = gl[2];
+        rec[2] = gl[3];
+        rec[3] = gl[4];
+        rec[4] = gl[5];
+        for (int lev = 0; lev < s.nlev; ++lev) {
+            const double nb = (double)(s.L / s.lev_L[lev]);
+            const double nboxes = nb * nb * nb;
+            for (int q = 0; q < kMoments; ++q) rec[5 + lev * kMoments + q] = lt[lev * kMoments + q] / nboxes;
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t k = nsamp[r];
-        if (s.series_cap > 0) {
-            double *rec = series_all + s.series_off + (k % s.series_cap) * s.rec_len;
-            rec[0] = (double)(*step + (uint64_t)koff);
-            rec[1] = gl[2];
-            rec[2] = gl[3];
-            rec[3] = gl[4];
-            rec[4] = gl[5];
-            for (int lev = 0; lev < s.nlev; ++lev) {
-                const double nb = (double)(s.L / s.lev_L[lev]);
-                const double nboxes = nb * nb * nb;
-                for (int q = 0; q < kMoments; ++q)
-                    rec[5 + lev * kMoments + q] = lev_tot[lev * kMoments + q] / nboxes;
-            }
-        }
-        nsamp[r] = k + 1;
-    }
+    nsamp[r] = k + 1;
 }
 
 }  // namespace lbfss
