@@ -14,9 +14,10 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   of its maximum (Eq. (PL-lowT) at m = M_L, Sec. IV C) and from its variance
   (Eqs. (chiL), (chiL-lowT)).
 - Structure factor, Sec. IV A, Eq. (G-comput): C(k) = N^-1 |sum_r phi e^{-ik.r}|^2,
-  here evaluated along the three lattice axes, k_m = 2 pi m / S,
-  1 <= m < S/2 (k = 0 vanishes by mass conservation; the zone-edge mode is
-  excluded).
+  evaluated along the three lattice axes, k_m = 2 pi m / S, 1 <= m < S/2
+  (k = 0 vanishes by mass conservation; the zone-edge mode is excluded), and
+  over the whole lattice (three-dimensional FFT), averaged over shells of
+  |m| for the Ornstein-Zernike fit of Eq. (CMF) (Sec. IV A).
 
 Arrays are flat, site = x + S*(y + S*z); reshaped to [z, y, x].
 """
@@ -69,6 +70,78 @@ def axis_structure_factor(phi, S):
     ms = np.arange(1, S // 2)
     E = np.exp(-2j * np.pi * np.outer(ms, n) / S)
     return np.array([np.abs(E @ P) ** 2 / S ** 3 for P in planes])
+
+
+def structure_factor_3d(phi, S):
+    """C(k) = N^-1 |sum_r phi(r) e^{-i k.r}|^2 at every k = 2 pi m / S, as an
+    [mz, my, mx] array (Eq. (G-comput)); the library FFT is the DFT."""
+    p = np.asarray(phi, dtype=np.float64).reshape(S, S, S)
+    return np.abs(np.fft.fftn(p)) ** 2 / S ** 3
+
+
+def folded_modes(S):
+    """Integer wave numbers m in (-S/2, S/2] of the FFT index order."""
+    i = np.arange(S)
+    return np.where(i <= S // 2, i, i - S)
+
+
+def lattice_laplacian_symbol(kx, ky, kz):
+    """-(discrete Laplacian) in Fourier space for the isotropic D3Q19 stencil
+    6 sum_i w_i (1 - cos k.c_i): ~k^2 at small k (the lattice k^2 of Eq. (CMF),
+    Sec. IV A)."""
+    axis = 2 * (3 - np.cos(kx) - np.cos(ky) - np.cos(kz)) / 3.0
+    diag = (12 - 2 * (np.cos(kx + ky) + np.cos(kx - ky) + np.cos(ky + kz) + np.cos(ky - kz)
+                      + np.cos(kz + kx) + np.cos(kz - kx))) / 6.0
+    return axis + diag
+
+
+def shells(S):
+    """Shell of every mode (array [mz, my, mx]): s = floor(|m| + 1/2) with m
+    folded into (-S/2, S/2]; the k = 0 mode is shell 0 and is excluded from
+    every shell average.  Returns (shell index array, number of shells incl. 0)."""
+    m = folded_modes(S).astype(np.float64)
+    mz, my, mx = np.meshgrid(m, m, m, indexing="ij")
+    r = np.sqrt(mx * mx + my * my + mz * mz)
+    sh = np.floor(r + 0.5).astype(np.int64)
+    return sh, int(sh.max()) + 1
+
+
+def shell_average(C, S):
+    """Per shell s >= 1: number of modes, sum of C, mean k^2 (continuum,
+    k = 2 pi m / S) and mean lattice Laplacian symbol over its modes."""
+    sh, ns = shells(S)
+    m = folded_modes(S) * (2 * np.pi / S)
+    kz, ky, kx = np.meshgrid(m, m, m, indexing="ij")
+    k2 = kx * kx + ky * ky + kz * kz
+    lap = lattice_laplacian_symbol(kx, ky, kz)
+    out = {"modes": np.zeros(ns, dtype=np.int64), "sum_C": np.zeros(ns), "k2": np.zeros(ns), "lap": np.zeros(ns)}
+    flat = sh.reshape(-1)
+    live = flat > 0
+    out["modes"] = np.bincount(flat[live], minlength=ns)
+    out["sum_C"] = np.bincount(flat[live], weights=np.asarray(C).reshape(-1)[live], minlength=ns)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        out["k2"] = np.bincount(flat[live], weights=k2.reshape(-1)[live], minlength=ns) / out["modes"]
+        out["lap"] = np.bincount(flat[live], weights=lap.reshape(-1)[live], minlength=ns) / out["modes"]
+    return out
+
+
+def oz_fit(mean_C, modes, x, kT, use):
+    """Ornstein-Zernike fit, Eq. (CMF): C = kT chi / (1 + xi^2 k^2), i.e.
+    1/C = A + B x with A = 1/(kT chi), B = xi^2 A, x the shell's k^2 (or the
+    lattice Laplacian symbol).  Weighted least squares over the shells
+    selected by ``use``, weight modes * C^2 (the inverse variance of 1/C for
+    a shell mean of `modes` exponentially distributed mode values).
+    Returns chi, xi (nan if B/A < 0), C0 = 1/A, A, B."""
+    y = 1.0 / np.asarray(mean_C, dtype=np.float64)[use]
+    xx = np.asarray(x, dtype=np.float64)[use]
+    w = np.asarray(modes, dtype=np.float64)[use] * np.asarray(mean_C, dtype=np.float64)[use] ** 2
+    S0, S1, S2 = w.sum(), (w * xx).sum(), (w * xx * xx).sum()
+    T0, T1 = (w * y).sum(), (w * xx * y).sum()
+    det = S0 * S2 - S1 * S1
+    A = (S2 * T0 - S1 * T1) / det
+    B = (S0 * T1 - S1 * T0) / det
+    xi = np.sqrt(B / A) if B / A >= 0 else float("nan")
+    return {"chi": 1.0 / (kT * A), "xi": xi, "C0": 1.0 / A, "A": A, "B": B}
 
 
 def box_histogram(m, bins, h):
@@ -131,7 +204,7 @@ class Accumulator:
     way the GPU library accumulates them; with ``hist_bins`` > 0 also the
     histogram of every level over [-hist_range, hist_range)."""
 
-    def __init__(self, S, n_levels=0, hist_bins=0, hist_range=0.0):
+    def __init__(self, S, n_levels=0, hist_bins=0, hist_range=0.0, sk3=False):
         self.S = S
         self.levels = levels(S, n_levels)
         self.n_samples = 0
@@ -140,6 +213,13 @@ class Accumulator:
         self.series = []
         self.hist_bins, self.hist_range = hist_bins, hist_range
         self.hist = {L: np.zeros(hist_bins + 2, dtype=np.int64) for L in self.levels} if hist_bins else {}
+        self.sk3 = np.zeros(shells(S)[1]) if sk3 else None
+        self.n_sk3 = 0
+
+    def add_sk3(self, rho):
+        """Shell sums of the 3D structure factor of one sample."""
+        self.sk3 += shell_average(structure_factor_3d(order_parameter(rho), self.S), self.S)["sum_C"]
+        self.n_sk3 += 1
 
     def add(self, rho, step=None, j=None):
         phi = order_parameter(rho)
