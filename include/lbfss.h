@@ -91,6 +91,10 @@ typedef struct {
     int32_t hist_bins; /* > 0: histogram every level's box values m over this many equal
                         * bins of [-hist_range, hist_range) (<= LB_MAX_HIST_BINS); 0 = none */
     double hist_range; /* half-width of the histogram, > 0 when hist_bins > 0 */
+    int32_t sk3_stride; /* > 0: on the samples at steps that are multiples of
+                         * sample_every * sk3_stride also accumulate the 3D structure
+                         * factor by shells (lb_sk3); 0 = never; equal in a batch */
+    int32_t reserved;   /* must be 0 */
 } lb_params;
 
 #define LB_MAX_HIST_BINS 4096
@@ -208,6 +212,39 @@ typedef struct {
  * moment sums; out: caller-owned, n_levels entries (coarsest first).
  * Synchronises.  LB_ESTATE if hist_bins = 0 or no sample was taken. */
 int lb_hist_estimates(lb_sim *sim, int replica, lb_hist_est *out);
+
+/* Three-dimensional structure factor (Sec. IV A, Eq. (G-comput)),
+ * C(k) = N^-1 |sum_r phi e^{-i k.r}|^2 at every k = 2 pi m / L, summed over
+ * shells s = floor(|m| + 1/2) with m folded into (-L/2, L/2]; shell 0 is
+ * k = 0 (excluded, no modes).  Shell geometry of one replica: n_shells
+ * (including shell 0), and, where the arrays are not NULL (n_shells entries
+ * each), the number of modes, the mean continuum k^2 and the mean lattice
+ * Laplacian symbol 6 sum_i w_i (1 - cos k.c_i) of every shell.
+ * LB_ESTATE if the replica has sk3_stride = 0. */
+int lb_sk3_shells(lb_sim *sim, int replica, int32_t *n_shells, int64_t *modes, double *k2_mean,
+                  double *lap_mean);
+
+/* Accumulated shell sums of C(k) (sum over the shell's modes and the samples
+ * taken, n_samples of them) of one replica; sum_C has n_shells entries.
+ * Synchronises.  LB_ESTATE if sk3_stride = 0. */
+int lb_sk3(lb_sim *sim, int replica, int64_t *n_samples, double *sum_C);
+
+typedef struct {
+    double chi;      /* 1 / (kT A): C(0) = kT chi */
+    double xi;       /* sqrt(B / A), NaN if B / A < 0 */
+    double C0;       /* 1 / A */
+    double A, B;     /* fit 1/C = A + B x */
+    int32_t n_used;  /* shells in the fit */
+    int32_t reserved;
+} lb_oz_t;
+
+/* Ornstein-Zernike fit of Eq. (CMF), C = kT chi / (1 + xi^2 k^2), to the
+ * shell means C_s = sum_C / (modes n_samples): weighted least squares of
+ * 1/C_s = A + B x_s over the shells s >= 1 with sqrt(mean k^2) <= k_max,
+ * weight modes_s C_s^2; x = mean k^2 (x_lattice = 0) or the mean lattice
+ * Laplacian symbol (x_lattice = 1), which Sec. IV A names as the k^2 of the
+ * discrete model.  LB_ESTATE without samples or with fewer than 2 shells. */
+int lb_oz_fit(lb_sim *sim, int replica, double k_max, int x_lattice, lb_oz_t *out);
 
 /* Current fields of one replica copied to host memory owned by the caller
  * (synchronising); any pointer may be NULL.  rho: L^3 doubles, j: 3 L^3

@@ -25,7 +25,7 @@ LB_MAX_LEVELS = 16
 EXPORTS = ("lb_create", "lb_create_batch", "lb_step", "lb_sync", "lb_moments", "lb_fields",
            "lb_set_populations", "lb_reset_moments", "lb_set_stream", "lb_set_allocator",
            "lb_set_plan", "lb_get_plan", "lb_tune", "lb_info", "lb_destroy", "lb_strerror",
-           "lb_histogram", "lb_hist_estimates")
+           "lb_histogram", "lb_hist_estimates", "lb_sk3_shells", "lb_sk3", "lb_oz_fit")
 
 
 class Params(ctypes.Structure):
@@ -34,7 +34,14 @@ class Params(ctypes.Structure):
                 ("init_sigma", ctypes.c_double), ("storage", ctypes.c_int32),
                 ("sample_every", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("series_capacity", ctypes.c_int32),
-                ("hist_bins", ctypes.c_int32), ("hist_range", ctypes.c_double)]
+                ("hist_bins", ctypes.c_int32), ("hist_range", ctypes.c_double),
+                ("sk3_stride", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class OzT(ctypes.Structure):
+    _fields_ = [("chi", ctypes.c_double), ("xi", ctypes.c_double), ("C0", ctypes.c_double),
+                ("A", ctypes.c_double), ("B", ctypes.c_double), ("n_used", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class HistEst(ctypes.Structure):
@@ -115,6 +122,9 @@ def lib():
     L.lb_destroy.restype = None
     L.lb_histogram.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint64)]
     L.lb_hist_estimates.argtypes = [vp, i32, ctypes.POINTER(HistEst)]
+    L.lb_sk3_shells.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), dp, dp]
+    L.lb_sk3.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp]
+    L.lb_oz_fit.argtypes = [vp, i32, ctypes.c_double, i32, ctypes.POINTER(OzT)]
     L.lb_strerror.argtypes = [i32]
     L.lb_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -167,10 +177,11 @@ def _use_torch():
 
 def make_params(a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, init_sigma=1e-3,
                 storage="fp32", sample_every=0, n_levels=0, force_off=False, series_capacity=0,
-                hist_bins=0, hist_range=0.0):
+                hist_bins=0, hist_range=0.0, sk3_stride=0):
     st = {"fp32": LB_FP32, "fp16": LB_FP16, LB_FP32: LB_FP32, LB_FP16: LB_FP16}[storage]
     return Params(a, b, kappa, rho_c, kT, tau, init_sigma, st, sample_every, n_levels,
-                  LB_FORCE_OFF if force_off else 0, series_capacity, int(hist_bins), float(hist_range))
+                  LB_FORCE_OFF if force_off else 0, series_capacity, int(hist_bins), float(hist_range),
+                  int(sk3_stride), 0)
 
 
 class Sim:
@@ -290,6 +301,32 @@ class Sim:
         arr = (HistEst * max(nlev, 1))()
         _check(lib().lb_hist_estimates(self._h, int(replica), arr), "lb_hist_estimates")
         return [{k: getattr(arr[i], k) for k, _ in HistEst._fields_ if k != "reserved"} for i in range(nlev)]
+
+    def sk3(self, replica=0):
+        """Shell sums of the 3D structure factor: n_samples, and per shell
+        (index = shell, 0 is k = 0) modes, mean k^2, mean lattice Laplacian
+        symbol, sum_C (over modes and samples) and mean_C."""
+        L_ = lib()
+        ns = ctypes.c_int32()
+        _check(L_.lb_sk3_shells(self._h, int(replica), ctypes.byref(ns), None, None, None), "lb_sk3_shells")
+        n = ns.value
+        modes = np.zeros(n, dtype=np.int64)
+        k2 = np.zeros(n)
+        lap = np.zeros(n)
+        _check(L_.lb_sk3_shells(self._h, int(replica), ctypes.byref(ns),
+                                modes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(k2), _dp(lap)),
+               "lb_sk3_shells")
+        sums = np.zeros(n)
+        nsamp = ctypes.c_int64()
+        _check(L_.lb_sk3(self._h, int(replica), ctypes.byref(nsamp), _dp(sums)), "lb_sk3")
+        with np.errstate(invalid="ignore", divide="ignore"):
+            mean = sums / (modes * max(nsamp.value, 1))
+        return {"n_samples": nsamp.value, "modes": modes, "k2": k2, "lap": lap, "sum_C": sums, "mean_C": mean}
+
+    def oz_fit(self, replica=0, k_max=1.0, lattice=False):
+        o = OzT()
+        _check(lib().lb_oz_fit(self._h, int(replica), float(k_max), int(bool(lattice)), ctypes.byref(o)), "lb_oz_fit")
+        return {k: getattr(o, k) for k, _ in OzT._fields_ if k != "reserved"}
 
     def reset_moments(self):
         _check(lib().lb_reset_moments(self._h), "lb_reset_moments")

@@ -14,6 +14,7 @@
 #include "../../include/lbfss.h"
 #include "lbfss_fused.hpp"
 #include "lbfss_sample.hpp"
+#include "lbfss_sk3.hpp"
 
 using namespace lbfss;
 
@@ -76,6 +77,21 @@ struct lb_sim {
     int64_t *d_nsamp = nullptr;
     unsigned long long *d_hist = nullptr;
     int64_t acc_len = 0, series_len = 0, hist_len = 0;
+
+    // three-dimensional structure factor (replicas with sk3_stride > 0)
+    int sk3_stride = 0;
+    struct Sk3Rep {
+        int n_shells = 0;
+        int64_t idx_off = 0, off_off = 0, acc_off = 0;
+        std::vector<int64_t> modes;
+        std::vector<double> k2, lap;
+    };
+    std::vector<Sk3Rep> sk3;
+    double2 *d_sk3A = nullptr, *d_sk3B = nullptr;
+    int32_t *d_sk3_idx = nullptr;
+    int64_t *d_sk3_off = nullptr, *d_sk3_n = nullptr;
+    double *d_sk3_acc = nullptr;
+    int64_t sk3_acc_len = 0;
 
     // fused plan work table
     FusedTile *d_tiles = nullptr;
@@ -163,6 +179,7 @@ int check_params(int L, const lb_params *p) {
     if (p->sample_every < 0 || p->n_levels < 0 || p->series_capacity < 0) return LB_EINVAL;
     if (p->hist_bins < 0 || p->hist_bins > LB_MAX_HIST_BINS) return LB_EINVAL;
     if (p->hist_bins > 0 && !(p->hist_range > 0 && std::isfinite(p->hist_range))) return LB_EINVAL;
+    if (p->sk3_stride < 0 || p->reserved != 0) return LB_EINVAL;
     return LB_OK;
 }
 
@@ -221,7 +238,28 @@ void enqueue_totals(lb_sim *s, int cur) {
     else launch_totals<float>(s, cur);
 }
 
-void enqueue_sample(lb_sim *s, int cur, int koff) {
+void enqueue_sk3(lb_sim *s) {
+    for (int r = 0; r < s->nrep; ++r) {
+        const SampDesc &d = s->hsd[r];
+        const lb_sim::Sk3Rep &q = s->sk3[r];
+        const int L = d.L, KX = sk3_tile(L), Lh = L / 2 + 1;
+        const unsigned ntile = (unsigned)((Lh + KX - 1) / KX);
+        const double *tw = s->d_ws + d.twid_off;
+        hipLaunchKernelGGL(k_sk3_x, dim3((unsigned)((int64_t)L * L)), dim3(kBlock), 0, s->stream, L,
+                           (const float *)s->d_snap + d.site_off, tw, s->d_sk3A);
+        hipLaunchKernelGGL(k_sk3_yz<1>, dim3((unsigned)L * ntile), dim3(kBlock), 0, s->stream, L, KX,
+                           (const double2 *)s->d_sk3A, s->d_sk3B, (double *)nullptr, tw,
+                           (const double *)(s->d_ws + d.glob_off));
+        hipLaunchKernelGGL(k_sk3_yz<2>, dim3((unsigned)L * ntile), dim3(kBlock), 0, s->stream, L, KX,
+                           (const double2 *)s->d_sk3B, (double2 *)nullptr, (double *)s->d_sk3A, tw,
+                           (const double *)(s->d_ws + d.glob_off));
+        hipLaunchKernelGGL(k_sk3_shells, dim3((unsigned)q.n_shells), dim3(kBlock), 0, s->stream, L,
+                           (const double *)s->d_sk3A, (const int32_t *)s->d_sk3_idx + q.idx_off,
+                           (const int64_t *)s->d_sk3_off + q.off_off, s->d_sk3_acc + q.acc_off, s->d_sk3_n + r);
+    }
+}
+
+void enqueue_sample(lb_sim *s, int cur, int koff, bool sk3) {
     enqueue_totals(s, cur);
     if (s->n_direct > 0)
         hipLaunchKernelGGL(k_box_direct, dim3((unsigned)ceil_div(s->n_direct, kBlock)), dim3(kBlock), 0,
@@ -250,6 +288,12 @@ void enqueue_sample(lb_sim *s, int cur, int koff) {
                            s->d_sd, s->max_nlev, s->d_ws, (const double *)s->d_parts, s->d_acc);
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)ceil_div(s->nrep, 64)), dim3(64), 0, s->stream, s->d_sd, s->nrep,
                        (const double *)s->d_ws, s->d_series, s->d_nsamp, (const uint64_t *)s->d_step, koff);
+    if (sk3) enqueue_sk3(s);
+}
+
+// Is the sample after step t (a multiple of sample_every) also a 3D sample?
+bool sk3_at(const lb_sim *s, int64_t t) {
+    return s->sk3_stride > 0 && t % ((int64_t)s->sample_every * s->sk3_stride) == 0;
 }
 
 bool sampling(const lb_sim *s) { return s->sample_every > 0; }
@@ -257,7 +301,7 @@ bool sampling(const lb_sim *s) { return s->sample_every > 0; }
 int64_t graph_period(const lb_sim *s) {
     int64_t P = 2;
     if (sampling(s)) {
-        const int64_t e = s->sample_every;
+        const int64_t e = (int64_t)s->sample_every * (s->sk3_stride > 0 ? s->sk3_stride : 1);
         P = (e % 2 == 0) ? e : 2 * e;
     }
     return P;
@@ -280,7 +324,7 @@ int build_graph(lb_sim *s, int G) {
     HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < G; ++k) {
         enqueue_step(s, k & 1, k);
-        if (sampling(s) && (k + 1) % s->sample_every == 0) enqueue_sample(s, (k + 1) & 1, k + 1);
+        if (sampling(s) && (k + 1) % s->sample_every == 0) enqueue_sample(s, (k + 1) & 1, k + 1, sk3_at(s, k + 1));
     }
     hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s->cap_stream, s->d_step, (int64_t)G);
     hipGraph_t graph = nullptr;
@@ -448,6 +492,86 @@ int build_sampling(lb_sim *s) {
     return LB_OK;
 }
 
+// Shell tables of the 3D structure factor: the half-space modes (kx = 0..L/2)
+// of every shell in ascending index order, and per shell the number of modes
+// of the whole space, the mean continuum k^2 and the mean lattice Laplacian
+// symbol (a half-space mode with 0 < kx < L/2 counts for itself and -k).
+int build_sk3(lb_sim *s) {
+    if (s->sk3_stride <= 0) return LB_OK;
+    std::vector<int32_t> idx_all;
+    std::vector<int64_t> off_all;
+    int64_t maxA = 0;
+    s->sk3.assign(s->nrep, lb_sim::Sk3Rep());
+    for (int r = 0; r < s->nrep; ++r) {
+        const int L = s->L[r], Lh = L / 2 + 1;
+        const int64_t nm = (int64_t)L * L * Lh;
+        maxA = std::max(maxA, nm);
+        const int ns = (int)std::floor(std::sqrt(3.0) * (L / 2) + 0.5) + 2;
+        lb_sim::Sk3Rep &q = s->sk3[r];
+        std::vector<int64_t> cnt(ns + 1, 0);
+        std::vector<double> k2(ns, 0.0), lap(ns, 0.0);
+        std::vector<int64_t> modes(ns, 0);
+        std::vector<int32_t> shell_of(nm);
+        const double two_pi_L = 2.0 * M_PI / L;
+        int smax = 0;
+        for (int kz = 0; kz < L; ++kz) {
+            const int mz = kz <= L / 2 ? kz : kz - L;
+            for (int ky = 0; ky < L; ++ky) {
+                const int my = ky <= L / 2 ? ky : ky - L;
+                for (int kx = 0; kx < Lh; ++kx) {
+                    const int mx = kx;
+                    const int64_t m = ((int64_t)kz * L + ky) * Lh + kx;
+                    const double rr = std::sqrt((double)mx * mx + (double)my * my + (double)mz * mz);
+                    const int sh = (int)std::floor(rr + 0.5);
+                    shell_of[m] = sh;
+                    smax = std::max(smax, sh);
+                    if (sh == 0) continue;
+                    const int w = (kx == 0 || (L % 2 == 0 && kx == L / 2)) ? 1 : 2;
+                    const double ax = mx * two_pi_L, ay = my * two_pi_L, az = mz * two_pi_L;
+                    const double sym = 2.0 * (3.0 - std::cos(ax) - std::cos(ay) - std::cos(az)) / 3.0 +
+                                       (12.0 - 2.0 * (std::cos(ax + ay) + std::cos(ax - ay) + std::cos(ay + az) +
+                                                      std::cos(ay - az) + std::cos(az + ax) + std::cos(az - ax))) /
+                                           6.0;
+                    cnt[sh + 1] += 1;
+                    modes[sh] += w;
+                    k2[sh] += w * (ax * ax + ay * ay + az * az);
+                    lap[sh] += w * sym;
+                }
+            }
+        }
+        q.n_shells = smax + 1;
+        q.modes.assign(modes.begin(), modes.begin() + q.n_shells);
+        q.k2.resize(q.n_shells);
+        q.lap.resize(q.n_shells);
+        for (int sh = 0; sh < q.n_shells; ++sh) {
+            q.k2[sh] = modes[sh] ? k2[sh] / modes[sh] : 0.0;
+            q.lap[sh] = modes[sh] ? lap[sh] / modes[sh] : 0.0;
+        }
+        for (int sh = 0; sh < q.n_shells; ++sh) cnt[sh + 1] += cnt[sh];
+        q.idx_off = (int64_t)idx_all.size();
+        q.off_off = (int64_t)off_all.size();
+        q.acc_off = s->sk3_acc_len;
+        s->sk3_acc_len += q.n_shells;
+        std::vector<int32_t> idx(cnt[q.n_shells]);
+        std::vector<int64_t> fill(cnt.begin(), cnt.begin() + q.n_shells);
+        for (int64_t m = 0; m < nm; ++m)
+            if (shell_of[m] > 0) idx[fill[shell_of[m]]++] = (int32_t)m;
+        idx_all.insert(idx_all.end(), idx.begin(), idx.end());
+        off_all.insert(off_all.end(), cnt.begin(), cnt.begin() + q.n_shells + 1);
+    }
+    int rc;
+    if ((rc = upload(s, &s->d_sk3_idx, idx_all))) return rc;
+    if ((rc = upload(s, &s->d_sk3_off, off_all))) return rc;
+    s->d_sk3A = (double2 *)dev_alloc(s, sizeof(double2) * maxA);
+    s->d_sk3B = (double2 *)dev_alloc(s, sizeof(double2) * maxA);
+    s->d_sk3_acc = (double *)dev_alloc(s, sizeof(double) * std::max<int64_t>(s->sk3_acc_len, 1));
+    s->d_sk3_n = (int64_t *)dev_alloc(s, sizeof(int64_t) * s->nrep);
+    if (!s->d_sk3A || !s->d_sk3B || !s->d_sk3_acc || !s->d_sk3_n) return LB_ENOMEM;
+    HIPCHK(hipMemsetAsync(s->d_sk3_acc, 0, sizeof(double) * std::max<int64_t>(s->sk3_acc_len, 1), s->stream));
+    HIPCHK(hipMemsetAsync(s->d_sk3_n, 0, sizeof(int64_t) * s->nrep, s->stream));
+    return LB_OK;
+}
+
 int build_tiles(lb_sim *s, int tx, int ty, int tz) {
     std::vector<FusedTile> tiles;
     if (make_fused_tiles(s->hdesc, tx, ty, tz, tiles) != 0) return LB_EINVAL;
@@ -467,7 +591,9 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
     for (int r = 0; r < n; ++r) {
         int rc = check_params(L[r], &p[r]);
         if (rc) return rc;
-        if (p[r].storage != p[0].storage || p[r].sample_every != p[0].sample_every) return LB_EINVAL;
+        if (p[r].storage != p[0].storage || p[r].sample_every != p[0].sample_every ||
+            p[r].sk3_stride != p[0].sk3_stride)
+            return LB_EINVAL;
     }
     lb_sim *s = new (std::nothrow) lb_sim();
     if (!s) return LB_ENOMEM;
@@ -484,6 +610,7 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
     s->nrep = n;
     s->storage = p[0].storage;
     s->sample_every = p[0].sample_every;
+    s->sk3_stride = p[0].sample_every > 0 ? p[0].sk3_stride : 0;
     std::vector<float> sigma0;
     for (int r = 0; r < n; ++r) {
         s->L.push_back(L[r]);
@@ -535,6 +662,7 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
                            s->nrep, s->total_sites, (const float *)s->d_drho, (float *)s->pop[0]);
     if (hipGetLastError() != hipSuccess) return fail(LB_EDEVICE);
     if ((rc = build_sampling(s))) return fail(rc);
+    if ((rc = build_sk3(s))) return fail(rc);
     // default plan: the fused kernel, with rows staging where it applies
     lb_plan def{LB_KERNEL_FUSED, 32, 8, 16, 0, 0};
     default_fused_tile(s->hdesc, def.tile_x, def.tile_y, def.tile_z);
@@ -586,7 +714,7 @@ int lb_step(lb_sim *s, int64_t n) {
         enqueue_step(s, cur, 0);
         hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s->stream, s->d_step, (int64_t)1);
         s->t += 1;
-        if (sampling(s) && s->t % s->sample_every == 0) enqueue_sample(s, cur ^ 1, 0);
+        if (sampling(s) && s->t % s->sample_every == 0) enqueue_sample(s, cur ^ 1, 0, sk3_at(s, s->t));
         n -= 1;
     }
     HIPCHK(hipGetLastError());
@@ -708,6 +836,69 @@ int lb_hist_estimates(lb_sim *s, int replica, lb_hist_est *out) {
     return LB_OK;
 }
 
+int lb_sk3_shells(lb_sim *s, int replica, int32_t *n_shells, int64_t *modes, double *k2_mean, double *lap_mean) {
+    if (!s || !n_shells || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    if (s->sk3_stride <= 0) return LB_ESTATE;
+    const lb_sim::Sk3Rep &q = s->sk3[replica];
+    *n_shells = q.n_shells;
+    for (int sh = 0; sh < q.n_shells; ++sh) {
+        if (modes) modes[sh] = q.modes[sh];
+        if (k2_mean) k2_mean[sh] = q.k2[sh];
+        if (lap_mean) lap_mean[sh] = q.lap[sh];
+    }
+    return LB_OK;
+}
+
+int lb_sk3(lb_sim *s, int replica, int64_t *n_samples, double *sum_C) {
+    if (!s || !n_samples || !sum_C || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    if (s->sk3_stride <= 0) return LB_ESTATE;
+    const lb_sim::Sk3Rep &q = s->sk3[replica];
+    HIPCHK(hipMemcpyAsync(sum_C, s->d_sk3_acc + q.acc_off, sizeof(double) * q.n_shells, hipMemcpyDeviceToHost,
+                          s->stream));
+    HIPCHK(hipMemcpyAsync(n_samples, s->d_sk3_n + replica, sizeof(int64_t), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return check_err(s);
+}
+
+// Weighted least squares of 1/C_s = A + B x_s, weight modes_s C_s^2 (Eq. (CMF)).
+int lb_oz_fit(lb_sim *s, int replica, double k_max, int x_lattice, lb_oz_t *out) {
+    if (!s || !out || replica < 0 || replica >= s->nrep || !(k_max > 0)) return LB_EINVAL;
+    if (s->sk3_stride <= 0) return LB_ESTATE;
+    const lb_sim::Sk3Rep &q = s->sk3[replica];
+    std::vector<double> sum(q.n_shells);
+    int64_t ns = 0;
+    int rc = lb_sk3(s, replica, &ns, sum.data());
+    if (rc) return rc;
+    if (ns <= 0) return LB_ESTATE;
+    double S0 = 0, S1 = 0, S2 = 0, T0 = 0, T1 = 0;
+    int used = 0;
+    for (int sh = 1; sh < q.n_shells; ++sh) {
+        if (q.modes[sh] <= 0 || std::sqrt(q.k2[sh]) > k_max) continue;
+        const double C = sum[sh] / ((double)q.modes[sh] * (double)ns);
+        if (!(C > 0)) continue;
+        const double x = x_lattice ? q.lap[sh] : q.k2[sh];
+        const double y = 1.0 / C, w = (double)q.modes[sh] * C * C;
+        S0 += w;
+        S1 += w * x;
+        S2 += w * x * x;
+        T0 += w * y;
+        T1 += w * x * y;
+        ++used;
+    }
+    if (used < 2) return LB_ESTATE;
+    const double det = S0 * S2 - S1 * S1;
+    const double A = (S2 * T0 - S1 * T1) / det, B = (S0 * T1 - S1 * T0) / det;
+    const double kT = s->P[replica].kT;
+    std::memset(out, 0, sizeof(*out));
+    out->A = A;
+    out->B = B;
+    out->C0 = 1.0 / A;
+    out->chi = 1.0 / (kT * A);
+    out->xi = B / A >= 0 ? std::sqrt(B / A) : (double)NAN;
+    out->n_used = used;
+    return LB_OK;
+}
+
 int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f) {
     if (!s || replica < 0 || replica >= s->nrep) return LB_EINVAL;
     const RepDesc &d = s->hdesc[replica];
@@ -783,6 +974,10 @@ int lb_reset_moments(lb_sim *s) {
     HIPCHK(hipMemsetAsync(s->d_series, 0, sizeof(double) * std::max<int64_t>(s->series_len, 1), s->stream));
     HIPCHK(hipMemsetAsync(s->d_nsamp, 0, sizeof(int64_t) * s->nrep, s->stream));
     HIPCHK(hipMemsetAsync(s->d_hist, 0, sizeof(unsigned long long) * std::max<int64_t>(s->hist_len, 1), s->stream));
+    if (s->sk3_stride > 0) {
+        HIPCHK(hipMemsetAsync(s->d_sk3_acc, 0, sizeof(double) * std::max<int64_t>(s->sk3_acc_len, 1), s->stream));
+        HIPCHK(hipMemsetAsync(s->d_sk3_n, 0, sizeof(int64_t) * s->nrep, s->stream));
+    }
     return LB_OK;
 }
 

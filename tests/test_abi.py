@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared():
     src = open(os.path.join(ROOT, "include", "lbfss.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +49,8 @@ def test_invalid_arguments_rejected_before_device(L):
                   (16, lbf.make_params(sample_every=-1)), (16, lbf.make_params(n_levels=-2)),
                   (16, lbf.make_params(hist_bins=-1)), (16, lbf.make_params(hist_bins=4097, hist_range=1.0)),
                   (16, lbf.make_params(hist_bins=10, hist_range=0.0)),
-                  (16, lbf.make_params(hist_bins=10, hist_range=float("inf")))]:
+                  (16, lbf.make_params(hist_bins=10, hist_range=float("inf"))),
+                  (16, lbf.make_params(sample_every=5, sk3_stride=-1))]:
         assert L.lb_create(L_, ctypes.byref(p), 1, ctypes.byref(h)) == lbf.LB_EINVAL
     bad = lbf.make_params()
     bad.storage = 7
@@ -63,4 +64,11 @@ def test_invalid_arguments_rejected_before_device(L):
     assert L.lb_sync(None) == lbf.LB_EINVAL
     assert L.lb_histogram(None, 0, None) == lbf.LB_EINVAL
     assert L.lb_hist_estimates(None, 0, None) == lbf.LB_EINVAL
+    assert L.lb_sk3(None, 0, None, None) == lbf.LB_EINVAL
+    assert L.lb_sk3_shells(None, 0, None, None, None, None) == lbf.LB_EINVAL
+    assert L.lb_oz_fit(None, 0, 1.0, 0, None) == lbf.LB_EINVAL
+    # sk3_stride must agree across a batch
+    Ls2 = (ctypes.c_int * 2)(8, 8)
+    P2 = (lbf.Params * 2)(lbf.make_params(sample_every=2, sk3_stride=1), lbf.make_params(sample_every=2))
+    assert L.lb_create_batch(2, Ls2, P2, (ctypes.c_uint64 * 2)(1, 2), ctypes.byref(h)) == lbf.LB_EINVAL
     L.lb_destroy(None)
