@@ -245,14 +245,25 @@ void enqueue_sk3(lb_sim *s) {
         const int L = d.L, KX = sk3_tile(L), Lh = L / 2 + 1;
         const unsigned ntile = (unsigned)((Lh + KX - 1) / KX);
         const double *tw = s->d_ws + d.twid_off;
-        hipLaunchKernelGGL(k_sk3_x, dim3((unsigned)((int64_t)L * L)), dim3(kBlock), 0, s->stream, L,
-                           (const float *)s->d_snap + d.site_off, tw, s->d_sk3A);
-        hipLaunchKernelGGL(k_sk3_yz<1>, dim3((unsigned)L * ntile), dim3(kBlock), 0, s->stream, L, KX,
-                           (const double2 *)s->d_sk3A, s->d_sk3B, (double *)nullptr, tw,
-                           (const double *)(s->d_ws + d.glob_off));
-        hipLaunchKernelGGL(k_sk3_yz<2>, dim3((unsigned)L * ntile), dim3(kBlock), 0, s->stream, L, KX,
-                           (const double2 *)s->d_sk3B, (double2 *)nullptr, (double *)s->d_sk3A, tw,
-                           (const double *)(s->d_ws + d.glob_off));
+        const double *gl = s->d_ws + d.glob_off;
+        if ((L & (L - 1)) == 0) {  // power of two: radix-2 FFT passes
+            const int KT = sk3_fft_tile(L), lg = __builtin_ctz((unsigned)L);
+            const unsigned gx = (unsigned)ceil_div((int64_t)L * L, KT), gyz = (unsigned)ceil_div((int64_t)L * Lh, KT);
+            hipLaunchKernelGGL(k_sk3_fft<0>, dim3(gx), dim3(kBlock), 0, s->stream, L, lg, KT,
+                               (const float *)s->d_snap + d.site_off, (const double2 *)nullptr, s->d_sk3A,
+                               (double *)nullptr, tw, gl);
+            hipLaunchKernelGGL(k_sk3_fft<1>, dim3(gyz), dim3(kBlock), 0, s->stream, L, lg, KT, (const float *)nullptr,
+                               (const double2 *)s->d_sk3A, s->d_sk3B, (double *)nullptr, tw, gl);
+            hipLaunchKernelGGL(k_sk3_fft<2>, dim3(gyz), dim3(kBlock), 0, s->stream, L, lg, KT, (const float *)nullptr,
+                               (const double2 *)s->d_sk3B, (double2 *)nullptr, (double *)s->d_sk3A, tw, gl);
+        } else {  // any L: direct DFT passes
+            hipLaunchKernelGGL(k_sk3_x, dim3((unsigned)((int64_t)L * L)), dim3(kBlock), 0, s->stream, L,
+                               (const float *)s->d_snap + d.site_off, tw, s->d_sk3A);
+            hipLaunchKernelGGL(k_sk3_yz<1>, dim3((unsigned)L * ntile), dim3(kBlock), 0, s->stream, L, KX,
+                               (const double2 *)s->d_sk3A, s->d_sk3B, (double *)nullptr, tw, gl);
+            hipLaunchKernelGGL(k_sk3_yz<2>, dim3((unsigned)L * ntile), dim3(kBlock), 0, s->stream, L, KX,
+                               (const double2 *)s->d_sk3B, (double2 *)nullptr, (double *)s->d_sk3A, tw, gl);
+        }
         hipLaunchKernelGGL(k_sk3_shells, dim3((unsigned)q.n_shells), dim3(kBlock), 0, s->stream, L,
                            (const double *)s->d_sk3A, (const int32_t *)s->d_sk3_idx + q.idx_off,
                            (const int64_t *)s->d_sk3_off + q.off_off, s->d_sk3_acc + q.acc_off, s->d_sk3_n + r);

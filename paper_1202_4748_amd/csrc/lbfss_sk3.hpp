@@ -6,13 +6,16 @@
 // phi = (rho - rho0)/rho0 differs from the density deviation of the snapshot
 // by a constant (k = 0 only) and the factor 1/rho0, so the transform runs on
 // the snapshot and C is scaled by 1/(N rho0^2).  The transform is separable:
-// a real-to-half-complex DFT along x (kx = 0..L/2), then complex DFTs along y
-// and z, each a direct O(L) sum per output with an FP64 twiddle table (index
-// (k n) mod L), so any L works.  Tiles of the input columns sit in LDS.  The
+// a real-to-half-complex transform along x (kx = 0..L/2), then complex ones
+// along y and z, all in FP64 with a twiddle table: radix-2 FFTs in LDS when L
+// is a power of two, otherwise direct O(L) sums per output (index (k n) mod
+// L), so any L works.  Tiles of the input columns sit in LDS.  The
 // shell sums reduce each shell's mode list in a fixed order, so they are
 // deterministic; a half-space mode with 0 < kx < L/2 stands for itself and
 // its mirror -k (weight 2).
 #pragma once
+
+#include <algorithm>
 
 #include "lbfss_step.hpp"
 
@@ -95,6 +98,79 @@ k_sk3_yz(int L, int KX, const double2 *__restrict__ in, double2 *__restrict__ ou
             out[((int64_t)a * L + kk) * Lh + kx0 + j] = make_double2(re, im);
         else
             C[((int64_t)kk * L + a) * Lh + kx0 + j] = (re * re + im * im) * scale;
+    }
+}
+
+// Radix-2 FFT passes for power-of-two L (the same three passes, O(L log L)
+// per column instead of O(L^2)): a tile of KT columns sits in LDS with the
+// element order along the transformed axis bit-reversed, followed by log2 L
+// in-place decimation-in-time butterfly stages (twiddle e^{-2 pi i q / m} =
+// table entry q L / m).  AXIS 0: real rows of the snapshot -> A[row][kx],
+// kx = 0..L/2; AXIS 1: A[z][y][kx] -> B[z][ky][kx]; AXIS 2: B[z][ky][kx] ->
+// C[kz][ky][kx] = |X|^2 / (N rho0^2).
+inline int sk3_fft_tile(int L) { return std::min(2048 / L, 64); }
+
+template <int AXIS>
+__global__ void __launch_bounds__(kBlock)
+k_sk3_fft(int L, int log2L, int KT, const float *__restrict__ drho, const double2 *__restrict__ in,
+          double2 *__restrict__ out, double *__restrict__ C, const double *__restrict__ twid,
+          const double *__restrict__ gl) {
+    __shared__ double2 T[2048];
+    __shared__ double cs[kSk3MaxL], sn[kSk3MaxL];
+    const int Lh = L / 2 + 1;
+    // columns: AXIS 0 -> the L^2 rows; AXIS 1, 2 -> (outer index a, kx)
+    const int64_t ncol = AXIS == 0 ? (int64_t)L * L : (int64_t)L * Lh;
+    const int64_t c0 = (int64_t)blockIdx.x * KT;
+    auto col_ok = [&](int j) { return c0 + j < ncol; };
+    // address of element n of column c
+    auto at = [&](int64_t c, int n) -> int64_t {
+        if (AXIS == 0) return c * L + n;
+        const int64_t a = c / Lh, kx = c - a * Lh;
+        return AXIS == 1 ? (a * L + n) * Lh + kx : ((int64_t)n * L + a) * Lh + kx;
+    };
+    for (int e = threadIdx.x; e < L * KT; e += kBlock) {
+        const int n = e / KT, j = e - n * KT;
+        const int slot = (int)(__brev((unsigned)n) >> (32 - log2L)) * KT + j;
+        double2 v = make_double2(0.0, 0.0);
+        if (col_ok(j)) {
+            if (AXIS == 0) v.x = (double)drho[at(c0 + j, n)];
+            else v = in[at(c0 + j, n)];
+        }
+        T[slot] = v;
+    }
+    for (int x = threadIdx.x; x < L; x += kBlock) {
+        cs[x] = twid[x];
+        sn[x] = twid[L + x];
+    }
+    __syncthreads();
+    for (int m = 2; m <= L; m <<= 1) {
+        const int half = m >> 1, step = L / m;
+        for (int b = threadIdx.x; b < (L / 2) * KT; b += kBlock) {
+            const int j = b % KT, bb = b / KT;
+            const int g = bb / half, q = bb - g * half;
+            const int i1 = (g * m + q) * KT + j, i2 = i1 + half * KT;
+            const double wr = cs[q * step], wi = -sn[q * step];
+            const double2 u = T[i1], v = T[i2];
+            const double tr = v.x * wr - v.y * wi, ti = v.x * wi + v.y * wr;
+            T[i1] = make_double2(u.x + tr, u.y + ti);
+            T[i2] = make_double2(u.x - tr, u.y - ti);
+        }
+        __syncthreads();
+    }
+    double scale = 0.0;
+    if (AXIS == 2) {
+        const double rho0 = gl[1];
+        scale = 1.0 / ((double)L * L * L * rho0 * rho0);
+    }
+    const int nout = AXIS == 0 ? Lh : L;
+    for (int e = threadIdx.x; e < nout * KT; e += kBlock) {
+        const int k = e / KT, j = e - k * KT;
+        if (!col_ok(j)) continue;
+        const double2 v = T[k * KT + j];
+        const int64_t c = c0 + j;
+        if (AXIS == 0) out[c * Lh + k] = v;
+        else if (AXIS == 1) out[at(c, k)] = v;
+        else C[at(c, k)] = (v.x * v.x + v.y * v.y) * scale;
     }
 }
 
