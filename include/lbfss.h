@@ -285,6 +285,58 @@ void lb_destroy(lb_sim *s);
 /* Static description of an error code. */
 const char *lb_strerror(int code);
 
+/* ------------------------------------------------------------------------
+ * The paper's own model (Sec. III A): fluctuating non-ideal D2Q9 lattice
+ * Boltzmann on a periodic L x L lattice (site = x + L y), with the
+ * Ginzburg-Landau thermodynamics carried by a modified equilibrium: its
+ * second moment is the pressure tensor of Eq. (press-th) plus rho u u and the
+ * Galilean correction of Eq. (holdych-cond); p0 = rho f0' - f0 with
+ * f0 = a d^2/2 + b d^4/4, d = rho - rho_c; zero third-order ghost moments
+ * and the fourth-order one 2 rho - 6 (p0 - kappa rho lap rho)
+ * - 3 kappa |grad rho|^2 (the projection of the paper's explicit
+ * equilibrium).  BGK relaxation, Eq. (lbe), with one tau; no body force, so
+ * mass and momentum are conserved exactly.  Noise on the six non-conserved
+ * moments with the covariance of Eq. (lbnoise) at the local squared sound
+ * speed c_s^2 = rho (a + 3 b d^2), drawn through its Cholesky factor from
+ * six normals of calls 0 and 1 of the same Philox generator (counter (site,
+ * step_lo, call, step_hi), key (seed_lo, seed_hi)).  Velocity order:
+ * 0 (0,0); 1 (1,0) 2 (-1,0) 3 (0,1) 4 (0,-1); 5 (1,1) 6 (-1,-1) 7 (1,-1)
+ * 8 (-1,1).  Populations stored in FP32, arithmetic FP32, spectra FP64.
+ * The calls follow the lb_* conventions (return codes, sticky LB_EUNSTABLE
+ * for rho <= 0, a non-finite value or a covariance that is not positive
+ * definite, i.e. c_s^2 >= 0.6).
+ * ------------------------------------------------------------------------ */
+typedef struct lb2_sim lb2_sim;
+
+typedef struct {
+    double a, b, kappa;  /* Landau r, u and the square-gradient coefficient */
+    double rho_c;        /* reference density, > 0 */
+    double kT;           /* noise temperature, >= 0 */
+    double tau;          /* relaxation time, > 1/2 */
+    double init_sigma;   /* standard deviation of the initial density, >= 0 */
+    int32_t sample_every; /* > 0: accumulate the spectra after every such step */
+    int32_t reserved;    /* must be 0 */
+} lb2_params;
+
+/* 4 <= L <= 2048.  The initial state is rho = rho_c + init_sigma g (Philox
+ * domain 1, call 0, first normal), u = 0, the equilibrium of that density. */
+int lb2_create(int L, const lb2_params *p, uint64_t seed, lb2_sim **out);
+int lb2_step(lb2_sim *s, int64_t n);   /* asynchronous */
+int lb2_sync(lb2_sim *s);
+/* rho (L^2), j ([2][L^2]) and f ([9][L^2]) of the current state; any may be
+ * NULL; caller-owned FP64 buffers; synchronises. */
+int lb2_fields(lb2_sim *s, double *rho, double *j, double *f);
+int lb2_set_populations(lb2_sim *s, const double *f);
+/* Accumulated spectra over the samples, each [ky][kx] (L^2 doubles, k index
+ * m in 0..L-1, wave number 2 pi m / L): S = <|drho_k|^2>/N, J_x, J_y =
+ * <|j_a,k|^2>/N, J_par, J_perp = the same for the projections of j_k on the
+ * direction of k (folded into (-L/2, L/2]) and across it (0 at k = 0):
+ * sums over samples, n_samples of them.  Any array may be NULL. */
+int lb2_spectra(lb2_sim *s, int64_t *n_samples, double *S, double *Jx, double *Jy, double *Jpar,
+                double *Jperp);
+int lb2_reset_spectra(lb2_sim *s);
+void lb2_destroy(lb2_sim *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,9 @@ LB_MAX_LEVELS = 16
 EXPORTS = ("lb_create", "lb_create_batch", "lb_step", "lb_sync", "lb_moments", "lb_fields",
            "lb_set_populations", "lb_reset_moments", "lb_set_stream", "lb_set_allocator",
            "lb_set_plan", "lb_get_plan", "lb_tune", "lb_info", "lb_destroy", "lb_strerror",
-           "lb_histogram", "lb_hist_estimates", "lb_sk3_shells", "lb_sk3", "lb_oz_fit")
+           "lb_histogram", "lb_hist_estimates", "lb_sk3_shells", "lb_sk3", "lb_oz_fit",
+           "lb2_create", "lb2_step", "lb2_sync", "lb2_fields", "lb2_set_populations", "lb2_spectra",
+           "lb2_reset_spectra", "lb2_destroy")
 
 
 class Params(ctypes.Structure):
@@ -36,6 +38,12 @@ class Params(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("series_capacity", ctypes.c_int32),
                 ("hist_bins", ctypes.c_int32), ("hist_range", ctypes.c_double),
                 ("sk3_stride", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Params2(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("rho_c", ctypes.c_double), ("kT", ctypes.c_double), ("tau", ctypes.c_double),
+                ("init_sigma", ctypes.c_double), ("sample_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class OzT(ctypes.Structure):
@@ -125,10 +133,19 @@ def lib():
     L.lb_sk3_shells.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), dp, dp]
     L.lb_sk3.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp]
     L.lb_oz_fit.argtypes = [vp, i32, ctypes.c_double, i32, ctypes.POINTER(OzT)]
+    L.lb2_create.argtypes = [i32, ctypes.POINTER(Params2), ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.lb2_step.argtypes = [vp, ctypes.c_int64]
+    L.lb2_sync.argtypes = [vp]
+    L.lb2_fields.argtypes = [vp, dp, dp, dp]
+    L.lb2_set_populations.argtypes = [vp, dp]
+    L.lb2_spectra.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp, dp, dp]
+    L.lb2_reset_spectra.argtypes = [vp]
+    L.lb2_destroy.argtypes = [vp]
+    L.lb2_destroy.restype = None
     L.lb_strerror.argtypes = [i32]
     L.lb_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("lb_destroy", "lb_strerror"):
+        if name not in ("lb_destroy", "lb_strerror", "lb2_destroy"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -351,3 +368,61 @@ class Sim:
         i = InfoT()
         _check(lib().lb_info(self._h, ctypes.byref(i)), "lb_info")
         return {k: getattr(i, k) for k, _ in i._fields_}
+
+
+class Sim2D:
+    """The paper's own D2Q9 model (Sec. III A) on an L x L lattice: the
+    Ginzburg-Landau pressure in a modified equilibrium, local-sound-speed
+    noise covariance (see the lb2_* section of include/lbfss.h)."""
+
+    def __init__(self, L, seed=0, a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, init_sigma=1e-3,
+                 sample_every=0):
+        L_ = lib()
+        _use_torch()
+        self.L = int(L)
+        p = Params2(a, b, kappa, rho_c, kT, tau, init_sigma, int(sample_every), 0)
+        h = ctypes.c_void_p()
+        _check(L_.lb2_create(self.L, ctypes.byref(p), ctypes.c_uint64(seed), ctypes.byref(h)), "lb2_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            try:
+                _lib.lb2_destroy(h)
+            finally:
+                self._h = None
+
+    def step(self, n=1):
+        _check(lib().lb2_step(self._h, int(n)), "lb2_step")
+
+    def sync(self):
+        _check(lib().lb2_sync(self._h), "lb2_sync")
+
+    def fields(self, f=False):
+        N = self.L * self.L
+        rho, j = np.zeros(N), np.zeros(2 * N)
+        ff = np.zeros(9 * N) if f else None
+        _check(lib().lb2_fields(self._h, _dp(rho), _dp(j), _dp(ff)), "lb2_fields")
+        out = {"rho": rho, "j": j.reshape(2, N)}
+        if f:
+            out["f"] = ff.reshape(9, N)
+        return out
+
+    def set_populations(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        _check(lib().lb2_set_populations(self._h, _dp(f)), "lb2_set_populations")
+
+    def spectra(self):
+        """Sums over samples of the spectra, each [ky, kx]: S, Jx, Jy, Jpar,
+        Jperp; and n_samples."""
+        N = self.L * self.L
+        arr = [np.zeros(N) for _ in range(5)]
+        n = ctypes.c_int64()
+        _check(lib().lb2_spectra(self._h, ctypes.byref(n), *[_dp(a) for a in arr]), "lb2_spectra")
+        out = {k: a.reshape(self.L, self.L) for k, a in zip(("S", "Jx", "Jy", "Jpar", "Jperp"), arr)}
+        out["n_samples"] = n.value
+        return out
+
+    def reset_spectra(self):
+        _check(lib().lb2_reset_spectra(self._h), "lb2_reset_spectra")

@@ -15,6 +15,7 @@
 #include "lbfss_fused.hpp"
 #include "lbfss_sample.hpp"
 #include "lbfss_sk3.hpp"
+#include "lbfss_d2q9.hpp"
 
 using namespace lbfss;
 
@@ -1130,3 +1131,205 @@ const char *lb_strerror(int code) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The paper's own D2Q9 model (kernels in lbfss_d2q9.hpp).
+// ---------------------------------------------------------------------------
+struct lb2_sim {
+    int L = 0;
+    lb2_params P{};
+    D2Desc D{};
+    hipStream_t stream = nullptr;
+    Allocator alloc;
+    std::vector<void *> blocks;
+    float *pop[2] = {nullptr, nullptr};
+    float *d_drho = nullptr;
+    int *d_err = nullptr;
+    double *d_twid = nullptr, *d_snap = nullptr, *d_acc = nullptr;
+    double2 *d_X = nullptr;
+    int64_t t = 0, n_samples = 0;
+};
+
+namespace {
+void *dev_alloc2(lb2_sim *s, size_t bytes) {
+    void *p = nullptr;
+    if (s->alloc.alloc) p = s->alloc.alloc(bytes, s->alloc.ctx);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (p) s->blocks.push_back(p);
+    return p;
+}
+}  // namespace
+
+void lb2_destroy(lb2_sim *s) {
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (void *p : s->blocks) {
+        if (s->alloc.free_) s->alloc.free_(p, s->alloc.ctx);
+        else (void)hipFree(p);
+    }
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int lb2_create(int L, const lb2_params *p, uint64_t seed, lb2_sim **out) {
+    if (!out || !p) return LB_EINVAL;
+    *out = nullptr;
+    if (L < 4 || L > 2048 || !(p->tau > 0.5) || !(p->kT >= 0) || !(p->kappa >= 0) || !(p->b >= 0) ||
+        !(p->rho_c > 0) || !(p->init_sigma >= 0) || !std::isfinite(p->a) || p->sample_every < 0 || p->reserved != 0)
+        return LB_EINVAL;
+    lb2_sim *s = new (std::nothrow) lb2_sim();
+    if (!s) return LB_ENOMEM;
+    s->alloc = g_alloc;
+    s->L = L;
+    s->P = *p;
+    auto fail = [&](int code) {
+        lb2_destroy(s);
+        return code;
+    };
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return fail(LB_EDEVICE);
+    const double gam = 1.0 - 1.0 / p->tau;
+    s->D.L = L;
+    s->D.a = (float)p->a;
+    s->D.b = (float)p->b;
+    s->D.kappa = (float)p->kappa;
+    s->D.rho_c = (float)p->rho_c;
+    s->D.gamma = (float)gam;
+    s->D.nu = (float)((p->tau - 0.5) / 3.0);
+    s->D.noise_amp = (float)std::sqrt(3.0 * p->kT * (1.0 - gam * gam));
+    s->D.key0 = (uint32_t)seed;
+    s->D.key1 = (uint32_t)(seed >> 32);
+    const int64_t N = (int64_t)L * L;
+    for (int b = 0; b < 2; ++b)
+        if (!(s->pop[b] = (float *)dev_alloc2(s, sizeof(float) * Q2 * N))) return fail(LB_ENOMEM);
+    s->d_drho = (float *)dev_alloc2(s, sizeof(float) * N);
+    s->d_err = (int *)dev_alloc2(s, sizeof(int));
+    s->d_twid = (double *)dev_alloc2(s, sizeof(double) * 2 * L);
+    if (!s->d_drho || !s->d_err || !s->d_twid) return fail(LB_ENOMEM);
+    if (p->sample_every > 0) {
+        s->d_snap = (double *)dev_alloc2(s, sizeof(double) * 3 * N);
+        s->d_X = (double2 *)dev_alloc2(s, sizeof(double2) * 3 * N);
+        s->d_acc = (double *)dev_alloc2(s, sizeof(double) * 5 * N);
+        if (!s->d_snap || !s->d_X || !s->d_acc) return fail(LB_ENOMEM);
+        if (hipMemsetAsync(s->d_acc, 0, sizeof(double) * 5 * N, s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    }
+    std::vector<double> tw(2 * L);
+    for (int k = 0; k < L; ++k) {
+        tw[k] = std::cos(2.0 * M_PI * k / L);
+        tw[L + k] = std::sin(2.0 * M_PI * k / L);
+    }
+    if (hipMemcpyAsync(s->d_twid, tw.data(), sizeof(double) * 2 * L, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemsetAsync(s->d_err, 0, sizeof(int), s->stream) != hipSuccess)
+        return fail(LB_EDEVICE);
+    const unsigned nb = (unsigned)ceil_div(N, kBlock);
+    hipLaunchKernelGGL(k2_init_density, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (float)p->init_sigma, s->d_drho);
+    hipLaunchKernelGGL(k2_init_populations, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->d_drho,
+                       s->pop[0]);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
+    *out = s;
+    return LB_OK;
+}
+
+namespace {
+int check2(lb2_sim *s) {
+    int h = 0;
+    if (hipMemcpyAsync(&h, s->d_err, sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+        return LB_EDEVICE;
+    return h ? LB_EUNSTABLE : LB_OK;
+}
+}  // namespace
+
+int lb2_step(lb2_sim *s, int64_t n) {
+    if (!s || n < 0) return LB_EINVAL;
+    const int64_t N = (int64_t)s->L * s->L;
+    const unsigned nb = (unsigned)ceil_div(N, kBlock);
+    for (int64_t k = 0; k < n; ++k) {
+        const int cur = (int)(s->t & 1);
+        hipLaunchKernelGGL(k2_density, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->pop[cur],
+                           s->d_drho);
+        hipLaunchKernelGGL(k2_collide, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->pop[cur],
+                           s->pop[cur ^ 1], (const float *)s->d_drho, (uint64_t)s->t, s->d_err);
+        s->t += 1;
+        if (s->P.sample_every > 0 && s->t % s->P.sample_every == 0) {
+            hipLaunchKernelGGL(k2_snap, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->pop[cur ^ 1],
+                               s->d_snap);
+            hipLaunchKernelGGL(k2_dft_rows, dim3((unsigned)(3 * s->L)), dim3(kBlock), 0, s->stream, s->L,
+                               (const double *)s->d_snap, (const double *)s->d_twid, s->d_X);
+            hipLaunchKernelGGL(k2_dft_cols, dim3(nb), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
+                               (const double *)s->d_twid, s->d_acc);
+            s->n_samples += 1;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? LB_OK : LB_EDEVICE;
+}
+
+int lb2_sync(lb2_sim *s) {
+    if (!s) return LB_EINVAL;
+    return check2(s);
+}
+
+int lb2_fields(lb2_sim *s, double *rho, double *j, double *f) {
+    if (!s) return LB_EINVAL;
+    const int64_t N = (int64_t)s->L * s->L;
+    const size_t need = (size_t)(rho ? N : 0) + (j ? 2 * N : 0) + (f ? Q2 * N : 0);
+    if (need == 0) return check2(s);
+    double *buf = (double *)dev_alloc2(s, sizeof(double) * need);
+    if (!buf) return LB_ENOMEM;
+    double *dr = rho ? buf : nullptr;
+    double *dj = j ? buf + (rho ? N : 0) : nullptr;
+    double *df = f ? buf + (rho ? N : 0) + (j ? 2 * N : 0) : nullptr;
+    int rc = LB_OK;
+    hipLaunchKernelGGL(k2_export, dim3((unsigned)ceil_div(N, kBlock)), dim3(kBlock), 0, s->stream, s->D,
+                       (const float *)s->pop[s->t & 1], dr, dj, df);
+    if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
+    if (rc == LB_OK && rho && hipMemcpyAsync(rho, dr, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream)) rc = LB_EDEVICE;
+    if (rc == LB_OK && j && hipMemcpyAsync(j, dj, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, s->stream)) rc = LB_EDEVICE;
+    if (rc == LB_OK && f && hipMemcpyAsync(f, df, sizeof(double) * Q2 * N, hipMemcpyDeviceToHost, s->stream)) rc = LB_EDEVICE;
+    if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
+    s->blocks.pop_back();
+    if (s->alloc.free_) s->alloc.free_(buf, s->alloc.ctx);
+    else (void)hipFree(buf);
+    return rc ? rc : check2(s);
+}
+
+int lb2_set_populations(lb2_sim *s, const double *f) {
+    if (!s || !f) return LB_EINVAL;
+    const int64_t N = (int64_t)s->L * s->L;
+    double *df = (double *)dev_alloc2(s, sizeof(double) * Q2 * N);
+    if (!df) return LB_ENOMEM;
+    int rc = LB_OK;
+    if (hipMemcpyAsync(df, f, sizeof(double) * Q2 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess) rc = LB_EDEVICE;
+    if (rc == LB_OK) {
+        hipLaunchKernelGGL(k2_import, dim3((unsigned)ceil_div(N, kBlock)), dim3(kBlock), 0, s->stream, s->D,
+                           (const double *)df, s->pop[s->t & 1]);
+        if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
+    }
+    if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
+    s->blocks.pop_back();
+    if (s->alloc.free_) s->alloc.free_(df, s->alloc.ctx);
+    else (void)hipFree(df);
+    return rc ? rc : check2(s);
+}
+
+int lb2_spectra(lb2_sim *s, int64_t *n_samples, double *S, double *Jx, double *Jy, double *Jpar, double *Jperp) {
+    if (!s || !n_samples) return LB_EINVAL;
+    if (s->P.sample_every <= 0) return LB_ESTATE;
+    const int64_t N = (int64_t)s->L * s->L;
+    double *dst[5] = {S, Jx, Jy, Jpar, Jperp};
+    for (int c = 0; c < 5; ++c)
+        if (dst[c] && hipMemcpyAsync(dst[c], s->d_acc + c * N, sizeof(double) * N, hipMemcpyDeviceToHost,
+                                     s->stream) != hipSuccess)
+            return LB_EDEVICE;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return LB_EDEVICE;
+    *n_samples = s->n_samples;
+    return check2(s);
+}
+
+int lb2_reset_spectra(lb2_sim *s) {
+    if (!s) return LB_EINVAL;
+    if (s->P.sample_every <= 0) return LB_ESTATE;
+    const int64_t N = (int64_t)s->L * s->L;
+    if (hipMemsetAsync(s->d_acc, 0, sizeof(double) * 5 * N, s->stream) != hipSuccess) return LB_EDEVICE;
+    s->n_samples = 0;
+    return LB_OK;
+}

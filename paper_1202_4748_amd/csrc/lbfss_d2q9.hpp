@@ -1,0 +1,345 @@
+// The paper's own model (Sec. III A): fluctuating non-ideal D2Q9 lattice
+// Boltzmann with the Ginzburg-Landau thermodynamics in a modified equilibrium
+// (the pressure tensor of Eq. (press-th) imposed on the equilibrium's second
+// moment, Eq. (holdych-cond)), BGK relaxation (Eq. (lbe)) and noise with the
+// local-sound-speed covariance of Eq. (lbnoise), drawn through its Cholesky
+// factor.
+//
+// Layout: populations [9][L^2] (site = x + L y), stored as deviations from
+// the rest state of density rho_c, whose equilibrium puts all mass at rest
+// (p0(rho_c) = 0): d_0 = f_0 - rho_c, d_i = f_i otherwise.  Moments are
+// taken in the weight-orthogonal basis 1, c_x, c_y, 3c^2 - 2, c_x^2 - c_y^2,
+// c_x c_y, (3c^2 - 4) c_x, (3c^2 - 4) c_y, 9c^4 - 15c^2 + 2 and handled as
+// deviations from the rest state's moments (rho_c, 0, 0, -2 rho_c, 0, 0, 0, 0,
+// 2 rho_c).  Velocity order: 0 (0,0); 1 (1,0) 2 (-1,0) 3 (0,1) 4 (0,-1);
+// 5 (1,1) 6 (-1,-1) 7 (1,-1) 8 (-1,1).
+#pragma once
+
+#include "lbfss_device.hpp"
+
+namespace lbfss {
+
+constexpr int Q2 = 9;
+
+struct D2Desc {
+    int32_t L, pad;
+    float a, b, kappa, rho_c;
+    float gamma;      // 1 - 1/tau
+    float nu;         // (tau - 1/2) / 3
+    float noise_amp;  // sqrt(3 kT (1/tau)(2 - 1/tau)); the noise scale is sqrt(rho) times this
+    uint32_t key0, key1;
+};
+
+__host__ __device__ constexpr int c2x(int i) { return i == 1 || i == 5 || i == 7 ? 1 : (i == 2 || i == 6 || i == 8 ? -1 : 0); }
+__host__ __device__ constexpr int c2y(int i) { return i == 3 || i == 5 || i == 8 ? 1 : (i == 4 || i == 6 || i == 7 ? -1 : 0); }
+__host__ __device__ constexpr float w2(int i) { return i == 0 ? 4.0f / 9.0f : (i < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
+
+// e_a(c_i) and the norms N_a = sum_i w_i e_a^2
+__host__ __device__ constexpr float e2(int a, int i) {
+    const int cx = c2x(i), cy = c2y(i), cc = cx * cx + cy * cy;
+    return a == 0 ? 1.0f
+         : a == 1 ? (float)cx
+         : a == 2 ? (float)cy
+         : a == 3 ? (float)(3 * cc - 2)
+         : a == 4 ? (float)(cx * cx - cy * cy)
+         : a == 5 ? (float)(cx * cy)
+         : a == 6 ? (float)((3 * cc - 4) * cx)
+         : a == 7 ? (float)((3 * cc - 4) * cy)
+                  : (float)(9 * cc * cc - 15 * cc + 2);
+}
+__host__ __device__ constexpr float n2(int a) {
+    return a == 0 ? 1.0f : a <= 2 ? 1.0f / 3.0f : a == 3 ? 4.0f : a == 4 ? 4.0f / 9.0f : a == 5 ? 1.0f / 9.0f
+         : a <= 7 ? 2.0f / 3.0f : 16.0f;
+}
+
+__device__ __forceinline__ int wrap2(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+// Pulled deviations of site (x, y): d_i(r - c_i).
+__device__ __forceinline__ void pull2(const float *__restrict__ pop, int L, int x, int y, float (&d)[Q2]) {
+    const int64_t N = (int64_t)L * L;
+#pragma unroll
+    for (int i = 0; i < Q2; ++i) {
+        const int xs = wrap2(x - c2x(i), L), ys = wrap2(y - c2y(i), L);
+        d[i] = pop[i * N + xs + (int64_t)L * ys];
+    }
+}
+
+__device__ __forceinline__ float drho2(const float (&d)[Q2]) {
+    return ((d[0] + (d[1] + d[2])) + (d[3] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8]));
+}
+
+// Density deviation of every site (pulled).
+__global__ void __launch_bounds__(kBlock)
+k2_density(D2Desc D, const float *__restrict__ pop, float *__restrict__ drho) {
+    const int L = D.L;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= (int64_t)L * L) return;
+    const int x = (int)(s % L), y = (int)(s / L);
+    float d[Q2];
+    pull2(pop, L, x, y, d);
+    drho[s] = drho2(d);
+}
+
+// One step at every site: pull, moments, equilibrium, relaxation, noise,
+// back-transform; the post-collision deviations go to pop_out unshifted.
+__global__ void __launch_bounds__(kBlock)
+k2_collide(D2Desc D, const float *__restrict__ pop, float *__restrict__ pop_out, const float *__restrict__ drho,
+           uint64_t t, int *__restrict__ err) {
+    const int L = D.L;
+    const int64_t N = (int64_t)L * L;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    const int x = (int)(s % L), y = (int)(s / L);
+    float d[Q2];
+    pull2(pop, L, x, y, d);
+    // moment deviations
+    float m[Q2];
+#pragma unroll
+    for (int a = 0; a < Q2; ++a) {
+        float v = 0.0f;
+#pragma unroll
+        for (int i = 0; i < Q2; ++i)
+            if (e2(a, i) != 0.0f) v += e2(a, i) * d[i];
+        m[a] = v;
+    }
+    const float dr = drho2(d);  // the same sum as the density array
+    const float rho = D.rho_c + dr;
+    // isotropic stencils on the density array
+    float gx = 0.0f, gy = 0.0f, lap = 0.0f;
+#pragma unroll
+    for (int i = 1; i < Q2; ++i) {
+        const float v = drho[wrap2(x + c2x(i), L) + (int64_t)L * wrap2(y + c2y(i), L)];
+        gx += 3.0f * w2(i) * (float)c2x(i) * v;
+        gy += 3.0f * w2(i) * (float)c2y(i) * v;
+        lap += 6.0f * w2(i) * (v - dr);
+    }
+    // thermodynamics of the Landau potential in d = rho - rho_c
+    const float d2 = dr * dr;
+    const float p0 = rho * (D.a * dr + D.b * d2 * dr) - (0.5f * D.a * d2 + 0.25f * D.b * d2 * d2);
+    const float cs2 = rho * (D.a + 3.0f * D.b * d2);
+    // equilibrium moments (deviations from the rest state)
+    const float inv_rho = 1.0f / rho;
+    const float ux = m[1] * inv_rho, uy = m[2] * inv_rho;
+    const float g2 = gx * gx + gy * gy, ug = ux * gx + uy * gy;
+    const float S = p0 - D.kappa * rho * lap;
+    const float iso = S - 0.5f * D.kappa * g2;
+    const float Pxx = iso + D.kappa * gx * gx + rho * ux * ux + D.nu * (2.0f * ux * gx + ug);
+    const float Pyy = iso + D.kappa * gy * gy + rho * uy * uy + D.nu * (2.0f * uy * gy + ug);
+    const float Pxy = D.kappa * gx * gy + rho * ux * uy + D.nu * (ux * gy + uy * gx);
+    float meq[Q2];
+    meq[3] = 3.0f * (Pxx + Pyy) - 2.0f * dr;
+    meq[4] = Pxx - Pyy;
+    meq[5] = Pxy;
+    meq[6] = 0.0f;
+    meq[7] = 0.0f;
+    meq[8] = 2.0f * dr - 6.0f * S - 3.0f * D.kappa * g2;
+#pragma unroll
+    for (int a = 3; a < Q2; ++a) m[a] = meq[a] + D.gamma * (m[a] - meq[a]);
+    // noise, Eq. (lbnoise), through the Cholesky factor of its c_s^2 block
+    bool bad = !(rho > 0.0f);
+    if (D.noise_amp > 0.0f) {
+        const float A = 4.0f * (2.0f - 3.0f * cs2), C = 12.0f * (cs2 - 1.0f / 3.0f),
+                    B = 16.0f * (1.25f - 0.75f * cs2);
+        const float L33 = __builtin_sqrtf(A), L83 = C / L33, R = B - L83 * L83;
+        bad |= !(A > 0.0f) || !(R > 0.0f);
+        const float L88 = __builtin_sqrtf(R);
+        const float sig = D.noise_amp * __builtin_sqrtf(rho);
+        const Words4 w0 = philox4x32_10((uint32_t)s, (uint32_t)t, 0u, (uint32_t)(t >> 32), D.key0, D.key1);
+        const Words4 w1 = philox4x32_10((uint32_t)s, (uint32_t)t, 1u, (uint32_t)(t >> 32), D.key0, D.key1);
+        const float r0 = bm_radius(uniform01(w0.v[0])), a0 = uniform01(w0.v[1]);
+        const float r1 = bm_radius(uniform01(w0.v[2])), a1 = uniform01(w0.v[3]);
+        const float r2 = bm_radius(uniform01(w1.v[0])), a2 = uniform01(w1.v[1]);
+        const float g0 = r0 * cos_rev(a0), g1 = r0 * sin_rev(a0);
+        const float g2n = r1 * cos_rev(a1), g3 = r1 * sin_rev(a1);
+        const float g4 = r2 * cos_rev(a2), g5 = r2 * sin_rev(a2);
+        m[3] += sig * L33 * g0;
+        m[4] += sig * (2.0f / 3.0f) * g1;
+        m[5] += sig * (1.0f / 3.0f) * g2n;
+        m[6] += sig * 0.816496580927726f * g3;  // sqrt(2/3)
+        m[7] += sig * 0.816496580927726f * g4;
+        m[8] += sig * (L83 * g0 + L88 * g5);
+    }
+    // back to populations, stored unshifted (the next step pulls)
+#pragma unroll
+    for (int i = 0; i < Q2; ++i) {
+        float v = 0.0f;
+#pragma unroll
+        for (int a = 0; a < Q2; ++a)
+            if (e2(a, i) != 0.0f) v += e2(a, i) * (m[a] * (1.0f / n2(a)));
+        pop_out[i * N + s] = w2(i) * v;
+    }
+    if (bad) *err = 1;
+}
+
+// Initial state: rho = rho_c + sigma0 g (generator domain 1, call 0), u = 0,
+// the equilibrium of that density (gradients of the density array).
+__global__ void __launch_bounds__(kBlock)
+k2_init_density(D2Desc D, float sigma0, float *__restrict__ drho) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= (int64_t)D.L * D.L) return;
+    const Words4 w = philox4x32_10((uint32_t)s, 0u, 1u << 16, 0u, D.key0, D.key1);
+    drho[s] = sigma0 * (bm_radius(uniform01(w.v[0])) * cos_rev(uniform01(w.v[1])));
+}
+
+__global__ void __launch_bounds__(kBlock)
+k2_init_populations(D2Desc D, const float *__restrict__ drho, float *__restrict__ pop) {
+    const int L = D.L;
+    const int64_t N = (int64_t)L * L;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    const int x = (int)(s % L), y = (int)(s / L);
+    const float dr = drho[s], rho = D.rho_c + dr;
+    float gx = 0.0f, gy = 0.0f, lap = 0.0f;
+#pragma unroll
+    for (int i = 1; i < Q2; ++i) {
+        const float v = drho[wrap2(x + c2x(i), L) + (int64_t)L * wrap2(y + c2y(i), L)];
+        gx += 3.0f * w2(i) * (float)c2x(i) * v;
+        gy += 3.0f * w2(i) * (float)c2y(i) * v;
+        lap += 6.0f * w2(i) * (v - dr);
+    }
+    const float d2 = dr * dr;
+    const float p0 = rho * (D.a * dr + D.b * d2 * dr) - (0.5f * D.a * d2 + 0.25f * D.b * d2 * d2);
+    const float g2 = gx * gx + gy * gy;
+    const float S = p0 - D.kappa * rho * lap, iso = S - 0.5f * D.kappa * g2;
+    float m[Q2] = {dr, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    const float Pxx = iso + D.kappa * gx * gx, Pyy = iso + D.kappa * gy * gy;
+    m[3] = 3.0f * (Pxx + Pyy) - 2.0f * dr;
+    m[4] = Pxx - Pyy;
+    m[5] = D.kappa * gx * gy;
+    m[8] = 2.0f * dr - 6.0f * S - 3.0f * D.kappa * g2;
+    // the state is read by pulling, f_i(r) = buffer_i(r - c_i)
+#pragma unroll
+    for (int i = 0; i < Q2; ++i) {
+        float v = 0.0f;
+#pragma unroll
+        for (int a = 0; a < Q2; ++a)
+            if (e2(a, i) != 0.0f) v += e2(a, i) * (m[a] * (1.0f / n2(a)));
+        pop[i * N + wrap2(x - c2x(i), L) + (int64_t)L * wrap2(y - c2y(i), L)] = w2(i) * v;
+    }
+}
+
+// Export: rho, j and the populations f_i in FP64 of the state at step t
+// (post-streaming: f_i(r) = buffer_i(r - c_i)).
+__global__ void __launch_bounds__(kBlock)
+k2_export(D2Desc D, const float *__restrict__ pop, double *__restrict__ rho, double *__restrict__ j,
+          double *__restrict__ f) {
+    const int L = D.L;
+    const int64_t N = (int64_t)L * L;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    const int x = (int)(s % L), y = (int)(s / L);
+    double r = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q2; ++i) {
+        const int xs = wrap2(x - c2x(i), L), ys = wrap2(y - c2y(i), L);
+        const double v = (double)pop[i * N + xs + (int64_t)L * ys] + (i == 0 ? (double)D.rho_c : 0.0);
+        r += v;
+        jx += c2x(i) * v;
+        jy += c2y(i) * v;
+        if (f) f[i * N + s] = v;
+    }
+    if (rho) rho[s] = r;
+    if (j) {
+        j[s] = jx;
+        j[N + s] = jy;
+    }
+}
+
+// Import: the state f_i(r) at step t into the buffer, buffer_i(r - c_i) = f_i(r).
+__global__ void __launch_bounds__(kBlock)
+k2_import(D2Desc D, const double *__restrict__ f, float *__restrict__ pop) {
+    const int L = D.L;
+    const int64_t N = (int64_t)L * L;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    const int x = (int)(s % L), y = (int)(s / L);
+#pragma unroll
+    for (int i = 0; i < Q2; ++i) {
+        const int xs = wrap2(x - c2x(i), L), ys = wrap2(y - c2y(i), L);
+        pop[i * N + xs + (int64_t)L * ys] = (float)(f[i * N + s] - (i == 0 ? (double)D.rho_c : 0.0));
+    }
+}
+
+// Sampling: density deviation and momentum of the state, FP64 [3][L^2].
+__global__ void __launch_bounds__(kBlock)
+k2_snap(D2Desc D, const float *__restrict__ pop, double *__restrict__ out) {
+    const int L = D.L;
+    const int64_t N = (int64_t)L * L;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    const int x = (int)(s % L), y = (int)(s / L);
+    double r = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q2; ++i) {
+        const int xs = wrap2(x - c2x(i), L), ys = wrap2(y - c2y(i), L);
+        const double v = (double)pop[i * N + xs + (int64_t)L * ys];
+        r += v;
+        jx += c2x(i) * v;
+        jy += c2y(i) * v;
+    }
+    out[s] = r;
+    out[N + s] = jx;
+    out[2 * N + s] = jy;
+}
+
+// Row transforms X_c[y][kx] = sum_x v_c[y][x] e^{-2 pi i kx x / L}: one
+// workgroup per (channel, row), twiddles cos, sin of 2 pi k / L.
+__global__ void __launch_bounds__(kBlock)
+k2_dft_rows(int L, const double *__restrict__ v, const double *__restrict__ twid, double2 *__restrict__ X) {
+    __shared__ double row[2048], cs[2048], sn[2048];
+    const int64_t r = blockIdx.x;  // channel * L + y
+    for (int x = threadIdx.x; x < L; x += kBlock) {
+        row[x] = v[r * L + x];
+        cs[x] = twid[x];
+        sn[x] = twid[L + x];
+    }
+    __syncthreads();
+    for (int kx = threadIdx.x; kx < L; kx += kBlock) {
+        double re = 0.0, im = 0.0;
+        int k = 0;
+        for (int x = 0; x < L; ++x) {
+            re += row[x] * cs[k];
+            im -= row[x] * sn[k];
+            k += kx;
+            if (k >= L) k -= L;
+        }
+        X[r * L + kx] = make_double2(re, im);
+    }
+}
+
+// Column transforms and accumulation, one thread per (ky, kx): per sample
+// S += |rho_k|^2 / N, Jx, Jy += |j_a,k|^2 / N, and the projections of j_k on
+// k (longitudinal) and across it (transverse); k = 0 has no direction (0).
+__global__ void __launch_bounds__(kBlock)
+k2_dft_cols(int L, const double2 *__restrict__ X, const double *__restrict__ twid, double *__restrict__ acc) {
+    const int64_t N = (int64_t)L * L;
+    const int64_t o = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (o >= N) return;
+    const int ky = (int)(o / L), kx = (int)(o - (int64_t)ky * L);
+    double re[3] = {0, 0, 0}, im[3] = {0, 0, 0};
+    int k = 0;
+    for (int y = 0; y < L; ++y) {
+        const double c = twid[k], sn = twid[L + k];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const double2 v = X[(int64_t)ch * N + (int64_t)y * L + kx];
+            re[ch] += v.x * c + v.y * sn;
+            im[ch] += v.y * c - v.x * sn;
+        }
+        k += ky;
+        if (k >= L) k -= L;
+    }
+    const double inv = 1.0 / (double)N;
+    const int mx = kx <= L / 2 ? kx : kx - L, my = ky <= L / 2 ? ky : ky - L;
+    const double kn = sqrt((double)mx * mx + (double)my * my);
+    const double hx = kn > 0 ? mx / kn : 0.0, hy = kn > 0 ? my / kn : 0.0;
+    const double pr = hx * re[1] + hy * re[2], pi = hx * im[1] + hy * im[2];
+    const double tr = -hy * re[1] + hx * re[2], ti = -hy * im[1] + hx * im[2];
+    acc[o] += (re[0] * re[0] + im[0] * im[0]) * inv;
+    acc[N + o] += (re[1] * re[1] + im[1] * im[1]) * inv;
+    acc[2 * N + o] += (re[2] * re[2] + im[2] * im[2]) * inv;
+    acc[3 * N + o] += (pr * pr + pi * pi) * inv;
+    acc[4 * N + o] += (tr * tr + ti * ti) * inv;
+}
+
+}  // namespace lbfss

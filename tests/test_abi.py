@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared():
     src = open(os.path.join(ROOT, "include", "lbfss.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(lb2?_[a-z0-9_]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
@@ -67,6 +67,13 @@ def test_invalid_arguments_rejected_before_device(L):
     assert L.lb_sk3(None, 0, None, None) == lbf.LB_EINVAL
     assert L.lb_sk3_shells(None, 0, None, None, None, None) == lbf.LB_EINVAL
     assert L.lb_oz_fit(None, 0, 1.0, 0, None) == lbf.LB_EINVAL
+    h2 = ctypes.c_void_p()
+    for L_, p2 in [(3, lbf.Params2(0, 0, 0, 1, 0, 1, 0, 0, 0)), (4096, lbf.Params2(0, 0, 0, 1, 0, 1, 0, 0, 0)),
+                   (16, lbf.Params2(0, 0, 0, 1, 0, 0.5, 0, 0, 0)), (16, lbf.Params2(0, -1, 0, 1, 0, 1, 0, 0, 0)),
+                   (16, lbf.Params2(0, 0, 0, 1, 0, 1, 0, -1, 0))]:
+        assert L.lb2_create(L_, ctypes.byref(p2), 1, ctypes.byref(h2)) == lbf.LB_EINVAL
+    assert L.lb2_step(None, 1) == lbf.LB_EINVAL
+    assert L.lb2_spectra(None, None, None, None, None, None, None) == lbf.LB_EINVAL
     # sk3_stride must agree across a batch
     Ls2 = (ctypes.c_int * 2)(8, 8)
     P2 = (lbf.Params * 2)(lbf.make_params(sample_every=2, sk3_stride=1), lbf.make_params(sample_every=2))
