@@ -22,7 +22,7 @@ _lib = None
 class _Params(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("rho_c", ctypes.c_double), ("kT", ctypes.c_double), ("tau", ctypes.c_double),
-                ("force_off", ctypes.c_int)]
+                ("force_off", ctypes.c_int), ("tau_bulk", ctypes.c_double), ("tau_ghost", ctypes.c_double)]
 
 
 def lib():
@@ -62,8 +62,11 @@ def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def params(a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, force_off=False, **_ignored):
-    return _Params(a, b, kappa, rho_c, kT, tau, 1 if force_off else 0)
+def params(a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, force_off=False, tau_bulk=0.0, tau_ghost=0.0,
+           **_ignored):
+    """tau_bulk, tau_ghost: relaxation times of moment 4 and of moments 10..18
+    (0: the same as tau)."""
+    return _Params(a, b, kappa, rho_c, kT, tau, 1 if force_off else 0, tau_bulk, tau_ghost)
 
 
 def lattice():
@@ -163,11 +166,11 @@ class Sim:
     """
 
     def __init__(self, S, seed, a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0,
-                 init_sigma=1e-3, force_off=False, nthreads=None, f=None, t=0):
+                 init_sigma=1e-3, force_off=False, nthreads=None, f=None, t=0, tau_bulk=0.0, tau_ghost=0.0):
         self.S = int(S)
         self.N = self.S ** 3
         self.seed = int(seed)
-        self.prm = params(a, b, kappa, rho_c, kT, tau, force_off)
+        self.prm = params(a, b, kappa, rho_c, kT, tau, force_off, tau_bulk, tau_ghost)
         self.nthreads = int(nthreads or default_threads())
         self.t = int(t)
         if f is None:

@@ -51,7 +51,18 @@ static const double CS2 = 1.0 / 3.0;
 typedef struct {
     double a, b, kappa, rho_c, kT, tau;
     int force_off; /* 1: F = 0 (ideal lattice gas, used by the tests) */
+    double tau_bulk, tau_ghost; /* relaxation times of moment 4 and of moments 10..18; 0 = tau */
 } orc_params;
+
+/* Relaxation time of moment a (>= 4): bulk (a = 4), shear (5..9, tau), ghosts
+ * (10..18).  One tau for all is the BGK collision of Eq. (lbe); separate
+ * rates are the multiple-relaxation-time form in which the paper sets all
+ * of them to one value (Sec. III B). */
+static double tau_of(const orc_params *p, int a) {
+    if (a == 4 && p->tau_bulk > 0.0) return p->tau_bulk;
+    if (a >= 10 && p->tau_ghost > 0.0) return p->tau_ghost;
+    return p->tau;
+}
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_EUNSTABLE = -4 };
 
@@ -346,13 +357,13 @@ int orc_collide_site(const orc_params *p, const double *f, const double *F, cons
     psi[8] = uy * Fz + uz * Fy;
     psi[9] = uz * Fx + ux * Fz;
 
-    double gam = 1.0 - 1.0 / p->tau;
     double mpost[Q];
     mpost[0] = rho;
     mpost[1] = m[1] + Fx;
     mpost[2] = m[2] + Fy;
     mpost[3] = m[3] + Fz;
     for (int a = 4; a < Q; ++a) {
+        double gam = 1.0 - 1.0 / tau_of(p, a);
         double sigma = sqrt(rho * p->kT * (1.0 - gam * gam) * NRM[a] / CS2);
         mpost[a] = meq[a] + gam * (m[a] - meq[a]) + 0.5 * (1.0 + gam) * psi[a] +
                    (g ? sigma * g[a - 4] : 0.0);
@@ -391,7 +402,9 @@ void orc_init(int S, double rho_c, double sigma0, uint64_t seed, double *f) {
 int orc_step(int S, const orc_params *p, uint64_t seed, uint64_t t, const double *fin, double *fout,
              int nthreads) {
     tables();
-    if (S < 1 || !(p->tau > 0.5)) return ORC_EINVAL;
+    if (S < 1 || !(p->tau > 0.5) || (p->tau_bulk != 0.0 && !(p->tau_bulk > 0.5)) ||
+        (p->tau_ghost != 0.0 && !(p->tau_ghost > 0.5)))
+        return ORC_EINVAL;
     int64_t N = (int64_t)S * S * S;
     double *rho = (double *)malloc(sizeof(double) * N);
     double *mu = (double *)malloc(sizeof(double) * N);

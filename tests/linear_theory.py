@@ -39,11 +39,40 @@ def lap_symbol(k):
     return 6.0 * np.sum(W * (1.0 - np.cos(C @ k)))
 
 
-def step_matrices(k, tau, a=0.0, kappa=0.0, rho0=1.0, kT=1.0, force_off=False):
-    """(A, Qn): f(t+1) = A f(t) + D theta, with D theta of covariance Qn."""
-    gam = 1.0 - 1.0 / tau
+def basis():
+    """E[a, i] = e_a(c_i), the weight-orthogonal D3Q19 moment basis: 1, c,
+    c^2 - 1, 3c_x^2 - c^2, c_y^2 - c_z^2, c_x c_y, c_y c_z, c_z c_x,
+    (3c^2 - 5) c, (c_y^2 - c_z^2) c_x, (c_z^2 - c_x^2) c_y, (c_x^2 - c_y^2) c_z,
+    3c^4 - 6c^2 + 1, (2c^2 - 3)(3c_x^2 - c^2), (2c^2 - 3)(c_y^2 - c_z^2)."""
+    cx, cy, cz = C.T
+    c2 = cx * cx + cy * cy + cz * cz
+    return np.array([np.ones(19), cx, cy, cz, c2 - 1, 3 * cx * cx - c2, cy * cy - cz * cz,
+                     cx * cy, cy * cz, cz * cx, (3 * c2 - 5) * cx, (3 * c2 - 5) * cy, (3 * c2 - 5) * cz,
+                     (cy * cy - cz * cz) * cx, (cz * cz - cx * cx) * cy, (cx * cx - cy * cy) * cz,
+                     3 * c2 * c2 - 6 * c2 + 1, (2 * c2 - 3) * (3 * cx * cx - c2), (2 * c2 - 3) * (cy * cy - cz * cz)])
+
+
+def gammas(tau, tau_bulk=0.0, tau_ghost=0.0):
+    """gamma_a = 1 - 1/tau_a per moment: bulk a = 4, shear 5..9, ghosts 10..18."""
+    t = np.full(19, float(tau))
+    if tau_bulk:
+        t[4] = tau_bulk
+    if tau_ghost:
+        t[10:] = tau_ghost
+    return 1.0 - 1.0 / t
+
+
+def step_matrices(k, tau, a=0.0, kappa=0.0, rho0=1.0, kT=1.0, force_off=False, tau_bulk=0.0, tau_ghost=0.0):
+    """(A, Qn): f(t+1) = A f(t) + D theta, with D theta of covariance Qn.
+    Separate relaxation times relax moment a with gamma_a: the collision is
+    sum_a gamma_a Pi_a with the projectors Pi_a = w e_a e_a^T / N_a."""
+    E = basis()
+    Nrm = (E * E * W).sum(axis=1)
+    proj = [W[:, None] * np.outer(E[a], E[a]) / Nrm[a] for a in range(19)]
+    gam_a = gammas(tau, tau_bulk, tau_ghost)
+    gam = gam_a[5]
     P = W[:, None] * (1.0 + 3.0 * (C @ C.T))
-    Cmat = P + gam * (np.eye(19) - P)
+    Cmat = P + sum(gam_a[a] * proj[a] for a in range(4, 19))
     Cmat = Cmat.astype(complex)
     if not force_off:
         G = grad_symbol(k)
@@ -54,7 +83,7 @@ def step_matrices(k, tau, a=0.0, kappa=0.0, rho0=1.0, kT=1.0, force_off=False):
     D = np.diag(np.exp(-1j * (C @ np.asarray(k, dtype=float))))
     A = D @ Cmat
     Wd = np.diag(W)
-    Qn = 3.0 * rho0 * kT * (1.0 - gam ** 2) * (Wd - P @ Wd)
+    Qn = 3.0 * rho0 * kT * sum((1.0 - gam_a[a] ** 2) * proj[a] @ Wd for a in range(4, 19))
     Qn = D @ Qn @ D.conj().T
     return A, Qn
 

@@ -39,3 +39,23 @@ def test_zone_edge_frozen():
     """The k = (pi, 0, 0) mode has a unit-modulus eigenvalue: no stationary
     state is defined there, and it is excluded from the comparisons."""
     assert lt.structure_factor((np.pi, 0, 0), 1.0, force_off=True, kT=1e-4) is None
+
+
+def test_moment_projectors_are_complete():
+    E = lt.basis()
+    Nrm = (E * E * lt.W).sum(axis=1)
+    total = sum(lt.W[:, None] * np.outer(E[a], E[a]) / Nrm[a] for a in range(19))
+    assert np.allclose(total, np.eye(19), atol=1e-14)
+
+
+@pytest.mark.parametrize("tau,tb,tg", [(0.8, 1.3, 0.6), (1.0, 0.55, 1.9), (1.4, 1.0, 1.0)])
+def test_ideal_gas_equipartition_separate_rates(tau, tb, tg):
+    """Every non-conserved moment relaxes with its own gamma_a and receives
+    noise of variance proportional to 1 - gamma_a^2: the ideal gas keeps
+    S(k) = 3 rho0 kT and <|j_a(k)|^2>/N = rho0 kT at every k for any rates."""
+    kT, rho0 = 1e-4, 1.1
+    for k in [(0.3, 0, 0), (1.0, 0.4, -0.2), (2.9, 2.0, 1.1)]:
+        s = lt.structure_factor(k, tau, kT=kT, rho0=rho0, force_off=True, tau_bulk=tb, tau_ghost=tg)
+        assert abs(s / (3 * rho0 * kT) - 1) < 1e-10
+        jv = lt.momentum_variance(k, tau, kT=kT, rho0=rho0, force_off=True, tau_bulk=tb, tau_ghost=tg)
+        assert np.allclose(jv / (rho0 * kT), 1, atol=1e-10)

@@ -78,3 +78,38 @@ def test_unstable_density_is_reported():
     f = -W * 0.1
     with pytest.raises(FloatingPointError):
         oracle.collide_site(oracle.params(tau=1.0), f, np.zeros(3))
+
+
+def test_separate_rates_touch_only_their_moments():
+    """Separate relaxation times (bulk: moment 4, ghosts: 10..18; the paper
+    sets every time to one value, Sec. III B): without noise and force, the
+    ghost time changes none of the moments 0..9 after collision, the bulk
+    time only moment 4, and equal times reproduce the BGK collision exactly."""
+    rng = np.random.default_rng(12)
+    _, _, T, n = oracle.lattice()
+    f = W * (1.05 + 0.05 * rng.standard_normal(19))
+    F = np.zeros(3)
+    base = oracle.collide_site(oracle.params(tau=0.8), f, F)
+    same = oracle.collide_site(oracle.params(tau=0.8, tau_bulk=0.8, tau_ghost=0.8), f, F)
+    assert np.array_equal(base, same)
+    ghost = oracle.collide_site(oracle.params(tau=0.8, tau_ghost=1.7), f, F)
+    assert np.allclose(T[:10] @ ghost, T[:10] @ base, atol=1e-15)
+    assert np.max(np.abs(T[10:] @ (ghost - base))) > 1e-4
+    bulk = oracle.collide_site(oracle.params(tau=0.8, tau_bulk=1.9), f, F)
+    d = T @ (bulk - base)
+    assert abs(d[4]) > 1e-5 and np.max(np.abs(np.delete(d, 4))) < 1e-15
+
+
+def test_noise_amplitude_with_separate_rates():
+    """Moment a gets sigma_a^2 = rho kT (1 - gamma_a^2) N_a / c_s^2 with its own gamma_a."""
+    rng = np.random.default_rng(13)
+    f = W * (1.1 + 0.05 * rng.standard_normal(19))
+    g = rng.standard_normal(16)
+    tau, tb, tg, kT = 0.8, 1.4, 0.6, 2e-4
+    prm = oracle.params(kT=kT, tau=tau, tau_bulk=tb, tau_ghost=tg)
+    theta = oracle.collide_site(prm, f, np.zeros(3), g) - oracle.collide_site(prm, f, np.zeros(3), np.zeros(16))
+    _, _, T, n = oracle.lattice()
+    taus = np.array([tb] + [tau] * 5 + [tg] * 9)
+    gam = 1 - 1 / taus
+    sig = np.sqrt(f.sum() * kT * (1 - gam ** 2) * n[4:] * 3)
+    assert np.allclose(T[4:] @ theta, sig * g[:15], atol=1e-15)

@@ -35,14 +35,16 @@ def _live_modes(S, **kw):
     return mask
 
 
-@pytest.mark.parametrize("tau", [1.0, 0.8])
-def test_ideal_gas_equipartition(tau):
+@pytest.mark.parametrize("tau,tb,tg", [(1.0, 0.0, 0.0), (0.8, 0.0, 0.0), (0.8, 1.3, 0.6)])
+def test_ideal_gas_equipartition(tau, tb, tg):
     """Force off: S(k) = 3 rho0 kT and <|j(k)|^2>/N = rho0 kT at all live k
-    (Eq. (vel-correl) and the ideal-gas compressibility)."""
+    (Eq. (vel-correl) and the ideal-gas compressibility), also with separate
+    bulk and ghost relaxation times (each moment's noise matches its own
+    rate)."""
     S, kT = 8, 1e-4
     _, rk, jk, _ = _run(S, 100, 3000, seed=5 + int(10 * tau), kT=kT, tau=tau, force_off=True,
-                        init_sigma=0.0, nthreads=4)
-    live = _live_modes(S, tau=tau, kT=kT, force_off=True)
+                        init_sigma=0.0, nthreads=4, tau_bulk=tb, tau_ghost=tg)
+    live = _live_modes(S, tau=tau, kT=kT, force_off=True, tau_bulk=tb, tau_ghost=tg)
     srho = rk[:, live].mean(axis=1)
     sj = jk[:, :, live].mean(axis=2)
     m, e = binned_mean(srho)
