@@ -13,9 +13,10 @@
  *            force, div P = rho grad(dF/dphi), with the ideal lattice-gas
  *            pressure cancelled; c_s^2 = 1/3)
  *   4. moment-space BGK collision with Guo forcing, u = (j + F/2)/rho, one
- *      relaxation time tau for every non-conserved moment    (Eq. (lbe))
+ *      relaxation time tau for every non-conserved moment (Eq. (lbe)), or
+ *      separate times for the bulk and ghost moments (tau_bulk, tau_ghost)
  *   5. Gaussian noise on the 15 non-conserved moments a with variance
- *      rho kT (1/tau)(2 - 1/tau) N_a / c_s^2   (Eq. (lbnoise) at c_s^2 = 1/3);
+ *      rho kT (1/tau_a)(2 - 1/tau_a) N_a / c_s^2 (Eq. (lbnoise) at c_s^2 = 1/3);
  *      the normals come from Philox4x32-10 (Salmon et al., SC'11) with key
  *      (seed_lo, seed_hi) and counter (site, step_lo, call, step_hi), call
  *      0..3, through Box-Muller on pairs of uniforms ((w >> 9) + 1/2) 2^-23
@@ -95,6 +96,9 @@ typedef struct {
                          * sample_every * sk3_stride also accumulate the 3D structure
                          * factor by shells (lb_sk3); 0 = never; equal in a batch */
     int32_t reserved;   /* must be 0 */
+    double tau_bulk;    /* relaxation time of the bulk moment c^2 - 1 (0: tau) */
+    double tau_ghost;   /* relaxation time of the ghost moments 10..18 (0: tau); the paper
+                         * sets all times to one value (Sec. III B), which is the default */
 } lb_params;
 
 #define LB_MAX_HIST_BINS 4096

@@ -37,7 +37,8 @@ class Params(ctypes.Structure):
                 ("sample_every", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("series_capacity", ctypes.c_int32),
                 ("hist_bins", ctypes.c_int32), ("hist_range", ctypes.c_double),
-                ("sk3_stride", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sk3_stride", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tau_bulk", ctypes.c_double), ("tau_ghost", ctypes.c_double)]
 
 
 class Params2(ctypes.Structure):
@@ -194,11 +195,11 @@ def _use_torch():
 
 def make_params(a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, init_sigma=1e-3,
                 storage="fp32", sample_every=0, n_levels=0, force_off=False, series_capacity=0,
-                hist_bins=0, hist_range=0.0, sk3_stride=0):
+                hist_bins=0, hist_range=0.0, sk3_stride=0, tau_bulk=0.0, tau_ghost=0.0):
     st = {"fp32": LB_FP32, "fp16": LB_FP16, LB_FP32: LB_FP32, LB_FP16: LB_FP16}[storage]
     return Params(a, b, kappa, rho_c, kT, tau, init_sigma, st, sample_every, n_levels,
                   LB_FORCE_OFF if force_off else 0, series_capacity, int(hist_bins), float(hist_range),
-                  int(sk3_stride), 0)
+                  int(sk3_stride), 0, float(tau_bulk), float(tau_ghost))
 
 
 class Sim:

@@ -181,6 +181,7 @@ int check_params(int L, const lb_params *p) {
     if (p->hist_bins < 0 || p->hist_bins > LB_MAX_HIST_BINS) return LB_EINVAL;
     if (p->hist_bins > 0 && !(p->hist_range > 0 && std::isfinite(p->hist_range))) return LB_EINVAL;
     if (p->sk3_stride < 0 || p->reserved != 0) return LB_EINVAL;
+    if ((p->tau_bulk != 0 && !(p->tau_bulk > 0.5)) || (p->tau_ghost != 0 && !(p->tau_ghost > 0.5))) return LB_EINVAL;
     return LB_OK;
 }
 
@@ -642,6 +643,13 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
         d.gamma = (float)gam;
         d.half1pg = (float)(0.5 * (1.0 + gam));
         d.noise_amp = (float)std::sqrt(3.0 * p[r].kT * (1.0 - gam * gam));
+        const double gb = p[r].tau_bulk > 0 ? 1.0 - 1.0 / p[r].tau_bulk : gam;
+        const double gg = p[r].tau_ghost > 0 ? 1.0 - 1.0 / p[r].tau_ghost : gam;
+        d.gamma_b = (float)gb;
+        d.half1pg_b = (float)(0.5 * (1.0 + gb));
+        d.noise_amp_b = (float)std::sqrt(3.0 * p[r].kT * (1.0 - gb * gb));
+        d.gamma_g = (float)gg;
+        d.noise_amp_g = (float)std::sqrt(3.0 * p[r].kT * (1.0 - gg * gg));
         d.key0 = (uint32_t)seeds[r];
         d.key1 = (uint32_t)(seeds[r] >> 32);
         s->hdesc.push_back(d);

@@ -25,10 +25,14 @@ struct RepDesc {
     int64_t N;         // L^3
     int64_t site_off;  // first site of the replica in the handle's flattened sites
     float a, b, kappa, rho_c;
-    float gamma;       // 1 - 1/tau
+    float gamma;       // 1 - 1/tau of the shear moments 5..9
     float half1pg;     // (1 + gamma) / 2, the Guo source factor 1 - 1/(2 tau)
     float noise_amp;   // sqrt(kT (1 - gamma^2) / c_s^2)
-    float pad;
+    float gamma_b;     // the same three for the bulk moment 4 (its own time tau_bulk)
+    float half1pg_b;
+    float noise_amp_b;
+    float gamma_g;     // ghost moments 10..18 (tau_ghost; no force source there)
+    float noise_amp_g;
     uint32_t key0, key1;  // Philox key: seed low and high words
 };
 
@@ -166,42 +170,45 @@ __device__ __forceinline__ float collide_site(const RepDesc &d, float (&r)[Q], f
     const float u2 = uxx + uyy + uzz;
     const float uF = ux * Fx + uy * Fy + uz * Fz;
 
-    // second-order equilibrium and Guo source moments (zero beyond a = 9)
+    // second-order equilibrium and Guo source moments (zero beyond a = 9);
+    // moment 4 relaxes with the bulk time, 5..9 with tau, 10..18 with the ghost time
     const float g = d.gamma, og = 1.0f - d.gamma, h = d.half1pg;
-    float p4 = og * (rho * u2) + g * m4 + h * (2.0f * uF);
+    const float gg = d.gamma_g;
+    float p4 = (1.0f - d.gamma_b) * (rho * u2) + d.gamma_b * m4 + d.half1pg_b * (2.0f * uF);
     float p5 = og * (rho * (3.0f * uxx - u2)) + g * m5 + h * (2.0f * (3.0f * ux * Fx - uF));
     float p6 = og * (rho * (uyy - uzz)) + g * m6 + h * (2.0f * (uy * Fy - uz * Fz));
     float p7 = og * (rho * ux * uy) + g * m7 + h * (ux * Fy + uy * Fx);
     float p8 = og * (rho * uy * uz) + g * m8 + h * (uy * Fz + uz * Fy);
     float p9 = og * (rho * uz * ux) + g * m9 + h * (uz * Fx + ux * Fz);
-    float p10 = g * m10, p11 = g * m11, p12 = g * m12;
-    float p13 = g * m13, p14 = g * m14, p15 = g * m15;
-    float p16 = g * m16, p17 = g * m17, p18 = g * m18;
+    float p10 = gg * m10, p11 = gg * m11, p12 = gg * m12;
+    float p13 = gg * m13, p14 = gg * m14, p15 = gg * m15;
+    float p16 = gg * m16, p17 = gg * m17, p18 = gg * m18;
 
     // thermal noise: sigma_a g_{a-4}, sigma_a = noise_amp sqrt(rho) sqrt(N_a);
     // generated and applied four normals (one Philox call) at a time
     {
-        const float amp = d.noise_amp * __builtin_amdgcn_sqrtf(fmaxf(rho, 0.0f));
+        const float srho = __builtin_amdgcn_sqrtf(fmaxf(rho, 0.0f));
+        const float amp = d.noise_amp * srho, amp_b = d.noise_amp_b * srho, amp_g = d.noise_amp_g * srho;
         float n[4];
         noise(0, n);  // normals 0..3 -> moments 4..7
-        p4 += amp * 0.81649658092772603f * n[0];   // sqrt(N_4),  N = 2/3
+        p4 += amp_b * 0.81649658092772603f * n[0];   // sqrt(N_4),  N = 2/3
         p5 += amp * 1.1547005383792515f * n[1];    // N = 4/3
         p6 += amp * 0.66666666666666667f * n[2];   // N = 4/9
         p7 += amp * 0.33333333333333333f * n[3];   // N = 1/9
         noise(1, n);  // normals 4..7 -> moments 8..11
         p8 += amp * 0.33333333333333333f * n[0];
         p9 += amp * 0.33333333333333333f * n[1];
-        p10 += amp * 0.81649658092772603f * n[2];  // N = 2/3
-        p11 += amp * 0.81649658092772603f * n[3];
+        p10 += amp_g * 0.81649658092772603f * n[2];  // N = 2/3
+        p11 += amp_g * 0.81649658092772603f * n[3];
         noise(2, n);  // normals 8..11 -> moments 12..15
-        p12 += amp * 0.81649658092772603f * n[0];
-        p13 += amp * 0.47140452079103169f * n[1];  // N = 2/9
-        p14 += amp * 0.47140452079103169f * n[2];
-        p15 += amp * 0.47140452079103169f * n[3];
+        p12 += amp_g * 0.81649658092772603f * n[0];
+        p13 += amp_g * 0.47140452079103169f * n[1];  // N = 2/9
+        p14 += amp_g * 0.47140452079103169f * n[2];
+        p15 += amp_g * 0.47140452079103169f * n[3];
         noise(3, n);  // normals 12..14 -> moments 16..18 (normal 15 unused)
-        p16 += amp * 1.4142135623730951f * n[0];   // N = 2
-        p17 += amp * 1.1547005383792515f * n[1];   // N = 4/3
-        p18 += amp * 0.66666666666666667f * n[2];  // N = 4/9
+        p16 += amp_g * 1.4142135623730951f * n[0];   // N = 2
+        p17 += amp_g * 1.1547005383792515f * n[1];   // N = 4/3
+        p18 += amp_g * 0.66666666666666667f * n[2];  // N = 4/9
     }
 
     // back-transform: r*_i = sum_a e_a(c_i) m*_a / N_a

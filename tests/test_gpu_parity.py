@@ -211,3 +211,20 @@ def test_rows_plan_needs_multiple_of_four():
         sim.set_plan("rows", (32, 8, 4))
     assert e.value.code == lbf.LB_EINVAL
     assert sim.plan() == before
+
+
+@pytest.mark.parametrize("kernel", ["split", "rows"])
+def test_separate_relaxation_times(kernel):
+    """Bulk and ghost moments with their own relaxation times (tau_bulk = 1.3,
+    tau_ghost = 0.6, tau = 0.8) against the oracle, every step of 30."""
+    lbf = require_gpu()
+    L = 12
+    say(f"separate rates L={L} {kernel}")
+    prm = dict(M0, tau=0.8, tau_bulk=1.3, tau_ghost=0.6, a=0.02, b=0.3)
+    sim = lbf.Sim(L, 17, **prm)
+    sim.set_plan(kernel, (16, 16, 5))
+    orc = oracle.Sim(L, 17, **prm)
+    for t in range(30):
+        sim.step(1)
+        orc.step(1)
+        _compare(sim, orc, TOL32, f"step {t + 1}")

@@ -71,11 +71,14 @@ def test_gaussian_statics_64():
         assert abs(U) < 5 * eU + 0.01, (Lb, U, eU)
 
 
-def test_ideal_gas_structure_factor_32():
+@pytest.mark.parametrize("rates", [{}, {"tau_bulk": 1.3, "tau_ghost": 0.6}])
+def test_ideal_gas_structure_factor_32(rates):
+    """Force off: S(k) = 3 kT at every axis mode, with one relaxation time and
+    with separate bulk and ghost times (fluctuation-dissipation per moment)."""
     lbf = require_gpu()
     L, kT = 32, 1e-4
-    say("ideal gas 32^3")
-    sim = lbf.Sim(L, 5, kT=kT, tau=0.8, force_off=True, init_sigma=0.0, sample_every=5)
+    say(f"ideal gas 32^3 {rates}")
+    sim = lbf.Sim(L, 5, kT=kT, tau=0.8, force_off=True, init_sigma=0.0, sample_every=5, **rates)
     sim.step(500)
     sks, _ = _windows(sim, 12, 1000, L)
     mean, err = binned_mean(sks, nbins=12)
