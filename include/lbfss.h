@@ -151,7 +151,7 @@ enum {
 typedef struct {
     int32_t kernel;      /* LB_KERNEL_SPLIT, _FUSED, _STAGED or _ROWS */
     int32_t tile_x;      /* fused: tile edge along x; (tile_x, tile_y) in {(32,8), (16,16),
-                          * (16,8), (64,4)}, (64,4) not staged or rows; clamped to L */
+                          * (16,8), (64,4)}, (64,4) not staged; clamped to L */
     int32_t tile_y;      /* fused: tile edge along y */
     int32_t tile_z;      /* fused: planes marched by one workgroup */
     int32_t graph_steps; /* > 0: capture this many steps (rounded up to even) in a

@@ -1027,7 +1027,7 @@ int lb_set_plan(lb_sim *s, const lb_plan *plan) {
     if (p.kernel == LB_KERNEL_FUSED || p.kernel == LB_KERNEL_STAGED || p.kernel == LB_KERNEL_ROWS) {
         if (p.kernel == LB_KERNEL_FUSED && !fused_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
         if (p.kernel == LB_KERNEL_STAGED && !staged_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
-        if (p.kernel == LB_KERNEL_ROWS && !staged_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
+        if (p.kernel == LB_KERNEL_ROWS && !rows_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
         if (p.kernel == LB_KERNEL_ROWS && !rows_ok(s)) return LB_EINVAL;
         int rc = build_tiles(s, p.tile_x, p.tile_y, p.tile_z);
         if (rc) return rc;
@@ -1053,10 +1053,10 @@ int lb_tune(lb_sim *s, int steps, lb_plan *best) {
     cands.push_back(lb_plan{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0});
     for (const auto &t : fused_tile_candidates(s->hdesc)) {
         cands.push_back(lb_plan{LB_KERNEL_FUSED, t[0], t[1], t[2], 0, 0});
-        if (s->storage == LB_FP32 && staged_tile_ok(t[0], t[1])) {
+        if (s->storage == LB_FP32 && staged_tile_ok(t[0], t[1]))
             cands.push_back(lb_plan{LB_KERNEL_STAGED, t[0], t[1], t[2], 0, 0});
-            if (rows_ok(s)) cands.push_back(lb_plan{LB_KERNEL_ROWS, t[0], t[1], t[2], 0, 0});
-        }
+        if (s->storage == LB_FP32 && rows_tile_ok(t[0], t[1]) && rows_ok(s))
+            cands.push_back(lb_plan{LB_KERNEL_ROWS, t[0], t[1], t[2], 0, 0});
     }
     const int64_t P = graph_period(s);
     const int gsteps = (int)(ceil_div(std::max<int64_t>(steps, 8), P) * P);

@@ -316,8 +316,11 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     constexpr int EX = TX + 4, EP = EX * (TY + 4);
     constexpr int MX = TX + 2, MP = MX * (TY + 2);
     constexpr int NH_MAX = 4 * (TX + TY) + 16;
-    static_assert(NH_MAX <= NT, "one halo site per thread");
-    constexpr int NHW = (NH_MAX + 63) / 64;  // waves that load halo sites
+    // per-site staging loads one halo site per thread; the rows staging only
+    // reads halo values from LDS and lets a thread take a second halo site
+    static_assert(NH_MAX <= NT || (ROWS && NH_MAX <= 2 * NT), "halo sites per thread");
+    constexpr bool H2 = NH_MAX > NT;
+    constexpr int NHW = (std::min(NH_MAX, NT) + 63) / 64;  // waves that load halo sites
     // rows mode: source rectangle of RW floats per row, CW 16-byte chunks
     constexpr int RW = TX + 8, CW = RW / 4, NL = CW * (TY + 4), NM = (NL + 63) / 64;
     constexpr int NS = ROWS ? 4 * NL : NT + NHW * 64;  // staging floats per population
@@ -347,27 +350,32 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     const int r_in = (iy + 2) * EX + (ix + 2);
     const int m_in = (iy + 1) * MX + (ix + 1);
 
-    // density halo site of this thread (tid < nhalo); others load a valid dummy
+    // density halo sites of this thread (h = tid, and h = tid + NT for wide
+    // tiles, while h < nhalo): two rows above, two below, two columns each side
     const int ew = nx + 4;
     const int nhalo = 4 * (nx + ny) + 16;
-    const bool has_h = tid < nhalo;
-    int hx = 0, hy = 0;
-    if (has_h) {
-        int h = tid;
+    auto halo_pos = [&](int h, int &px, int &py) {
         if (h < 2 * ew) {
-            hy = h / ew;
-            hx = h - hy * ew;
+            py = h / ew;
+            px = h - py * ew;
         } else if (h < 4 * ew) {
             h -= 2 * ew;
-            hy = ny + 2 + h / ew;
-            hx = h - (h / ew) * ew;
+            py = ny + 2 + h / ew;
+            px = h - (h / ew) * ew;
         } else {
             h -= 4 * ew;
-            hy = 2 + (h >> 2);
+            py = 2 + (h >> 2);
             const int k = h & 3;
-            hx = k < 2 ? k : nx + k;
+            px = k < 2 ? k : nx + k;
         }
-    }
+    };
+    const bool has_h = tid < nhalo;
+    int hx = 0, hy = 0;
+    if (has_h) halo_pos(tid, hx, hy);
+    const bool has_h2 = H2 && tid + NT < nhalo;
+    int hx2 = 0, hy2 = 0;
+    if (has_h2) halo_pos(tid + NT, hx2, hy2);
+    const int r_h2 = hy2 * EX + hx2;
     PlaneOffs ho;
     ho.set(wrap_near(tl.x0 - 2 + hx, L), wrap_near(tl.y0 - 2 + hy, L), L, sizeof(float));
     const int r_h = hy * EX + hx;
@@ -444,6 +452,7 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     // LDS slot of the pulled value q of the tile site / the halo site
     auto slot_in = [&](int q) { return ROWS ? (iy + 2) * RW + ix + 4 - cx_of(q) : tid; };
     auto slot_h = [&](int q) { return ROWS ? hy * RW + hx + 2 - cx_of(q) : NT + tid; };
+    auto slot_h2 = [&](int q) { return hy2 * RW + hx2 + 2 - cx_of(q); };
 
     bool bad = false;
     float A[Q], B[Q], C[Q];
@@ -467,6 +476,12 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
 #pragma unroll
                 for (int q = 0; q < Q; ++q) h[q] = s_stage[q][slot_h(q)];
                 rs[r_h] = drho_of(h);
+            }
+            if (H2 && has_h2) {
+                float h[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) h[q] = s_stage[q][slot_h2(q)];
+                rs[r_h2] = drho_of(h);
             }
         }
         __syncthreads();
@@ -609,6 +624,9 @@ inline bool staged_tile_ok(int tx, int ty) {
     return (tx == 16 && ty == 16) || (tx == 32 && ty == 8) || (tx == 16 && ty == 8);
 }
 
+// the rows staging also takes 64 x 4 tiles (two halo sites for some threads)
+inline bool rows_tile_ok(int tx, int ty) { return staged_tile_ok(tx, ty) || (tx == 64 && ty == 4); }
+
 
 template <bool ROWS>
 void launch_fused_staged(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const float *in, float *out,
@@ -618,6 +636,9 @@ void launch_fused_staged(const RepDesc *desc, const FusedTile *tiles, int n_tile
                            out, step, koff, err);
     else if (tx == 16 && ty == 8)
         hipLaunchKernelGGL((k_fused_staged<16, 8, ROWS>), dim3(n_tiles), dim3(128), 0, stream, desc, tiles, in,
+                           out, step, koff, err);
+    else if (ROWS && tx == 64 && ty == 4)
+        hipLaunchKernelGGL((k_fused_staged<64, 4, true>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
                            out, step, koff, err);
     else
         hipLaunchKernelGGL((k_fused_staged<32, 8, ROWS>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,

@@ -67,7 +67,7 @@ def test_config0_100_steps(kernel):
                                            (12, "rows", (16, 16, 5)), (12, "staged", (16, 8, 5)),
                                            (20, "rows", (16, 16, 16)), (37, "staged", (32, 8, 16)),
                                            (40, "rows", (32, 8, 7)), (44, "rows", (16, 8, 9)),
-                                           (36, "fused", (64, 4, 5))])
+                                           (36, "fused", (64, 4, 5)), (36, "rows", (64, 4, 5))])
 def test_ragged_sizes(L, kernel, tile):
     """Sizes not divisible by the tile (partial tiles, wrap-around halos, the
     source rows of the rows staging wrapping more than once on L = 4)."""
@@ -139,7 +139,8 @@ def test_plans_bit_identical():
     for kernel, tile, g in [("split", (0, 0, 0), 0), ("fused", (16, 16, 8), 0), ("fused", (32, 8, 24), 0),
                             ("fused", (32, 8, 5), 6), ("split", (0, 0, 0), 4), ("fused", (64, 4, 7), 0),
                             ("staged", (32, 8, 9), 0), ("staged", (16, 16, 24), 0), ("staged", (16, 8, 5), 4),
-                            ("rows", (32, 8, 9), 0), ("rows", (16, 16, 24), 6), ("rows", (16, 8, 5), 0)]:
+                            ("rows", (32, 8, 9), 0), ("rows", (16, 16, 24), 6), ("rows", (16, 8, 5), 0),
+                            ("rows", (64, 4, 7), 0)]:
         sim = lbf.Sim(L, 11, **M0)
         sim.set_plan(kernel, tile, g)
         sim.step(13)
