@@ -101,8 +101,13 @@ struct lb_sim {
 
     int64_t t = 0;
     lb_plan plan{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0};
-    hipGraphExec_t gexec = nullptr;
-    int g_steps = 0;
+    // captured step loops, one per starting condition: [1] begins with a
+    // sample pending (its snapshot is written by the first step kernel)
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int g_steps[2] = {0, 0};
+    // a sample of the current state is due but not yet taken: the next step
+    // kernel writes its snapshot, or a flush takes it with a snapshot pass
+    bool pending = false;
 };
 
 // The rows staging copies 16-byte chunks that must not straddle the periodic
@@ -186,22 +191,24 @@ int check_params(int L, const lb_params *p) {
 }
 
 template <typename T>
-void launch_step(lb_sim *s, int cur, int koff) {
+void launch_step(lb_sim *s, int cur, int koff, float *snap) {
     const T *in = (const T *)s->pop[cur];
     T *out = (T *)s->pop[cur ^ 1];
+    const int64_t total = s->total_sites;
     if ((s->plan.kernel == LB_KERNEL_STAGED || s->plan.kernel == LB_KERNEL_ROWS) && s->n_tiles > 0 &&
         std::is_same<T, float>::value) {
         if (s->plan.kernel == LB_KERNEL_ROWS)
             launch_fused_staged<true>(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out, s->d_step,
-                                      koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream);
+                                      koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream, snap, total);
         else
             launch_fused_staged<false>(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out,
-                                       s->d_step, koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream);
+                                       s->d_step, koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream, snap,
+                                       total);
         return;
     }
     if (s->plan.kernel != LB_KERNEL_SPLIT && s->n_tiles > 0) {
         launch_fused<T>(s->d_desc, s->d_tiles, s->n_tiles, in, out, s->d_step, koff, s->d_err,
-                        s->plan.tile_x, s->plan.tile_y, s->stream);
+                        s->plan.tile_x, s->plan.tile_y, s->stream, snap, total);
         return;
     }
     const int64_t nb = ceil_div(s->total_sites, kBlock);
@@ -211,20 +218,27 @@ void launch_step(lb_sim *s, int cur, int koff) {
                        s->total_sites, (const float *)s->d_drho, s->d_mu);
     hipLaunchKernelGGL(k_collide<T>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
                        s->total_sites, in, out, (const float *)s->d_drho, (const float *)s->d_mu,
-                       (const uint64_t *)s->d_step, koff, s->d_err);
+                       (const uint64_t *)s->d_step, koff, s->d_err, snap);
 }
 
-void enqueue_step(lb_sim *s, int cur, int koff) {
-    if (s->storage == LB_FP16) launch_step<__half>(s, cur, koff);
-    else launch_step<float>(s, cur, koff);
+// One step; with snap set the step kernel also writes the sample snapshot of
+// the state it starts from.
+void enqueue_step(lb_sim *s, int cur, int koff, float *snap = nullptr) {
+    if (s->storage == LB_FP16) launch_step<__half>(s, cur, koff, snap);
+    else launch_step<float>(s, cur, koff, snap);
 }
 
-// Reduction stages shared by sampling and by lb_moments' current totals.
+// Snapshot pass over the populations (when no step kernel wrote it).
 template <typename T>
-void launch_totals(lb_sim *s, int cur) {
+void launch_snapshot(lb_sim *s, int cur) {
     const int64_t nb = ceil_div(s->total_sites, kBlock);
     hipLaunchKernelGGL(k_snapshot<T>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
                        s->total_sites, (const T *)s->pop[cur], s->d_snap);
+}
+
+// Reduction stages over the snapshot, shared by sampling and by lb_moments'
+// current totals.
+void enqueue_reductions(lb_sim *s) {
     hipLaunchKernelGGL(k_rows, dim3((unsigned)ceil_div(s->n_rows, kBlock / 64)), dim3(kBlock), 0, s->stream,
                        s->d_sd, s->d_cum_rows, s->nrep, s->total_sites, (const float *)s->d_snap, s->d_ws);
     hipLaunchKernelGGL(k_cols, dim3((unsigned)ceil_div(s->n_cols, kBlock)), dim3(kBlock), 0, s->stream,
@@ -236,8 +250,9 @@ void launch_totals(lb_sim *s, int cur) {
 }
 
 void enqueue_totals(lb_sim *s, int cur) {
-    if (s->storage == LB_FP16) launch_totals<__half>(s, cur);
-    else launch_totals<float>(s, cur);
+    if (s->storage == LB_FP16) launch_snapshot<__half>(s, cur);
+    else launch_snapshot<float>(s, cur);
+    enqueue_reductions(s);
 }
 
 void enqueue_sk3(lb_sim *s) {
@@ -272,8 +287,10 @@ void enqueue_sk3(lb_sim *s) {
     }
 }
 
-void enqueue_sample(lb_sim *s, int cur, int koff, bool sk3) {
-    enqueue_totals(s, cur);
+// Sample stages after the snapshot reductions: box sums, level moments and
+// histograms, axis S(k), series record, 3D S(k).  koff places the record's
+// step relative to the device step counter.
+void enqueue_sample_rest(lb_sim *s, int koff, bool sk3) {
     if (s->n_direct > 0)
         hipLaunchKernelGGL(k_box_direct, dim3((unsigned)ceil_div(s->n_direct, kBlock)), dim3(kBlock), 0,
                            s->stream, s->d_sd, s->d_cum_direct, s->nrep, (const float *)s->d_snap, s->d_ws);
@@ -309,6 +326,14 @@ bool sk3_at(const lb_sim *s, int64_t t) {
     return s->sk3_stride > 0 && t % ((int64_t)s->sample_every * s->sk3_stride) == 0;
 }
 
+// Take a pending sample of the current state with its own snapshot pass.
+void flush_pending(lb_sim *s) {
+    if (!s->pending) return;
+    enqueue_totals(s, (int)(s->t & 1));
+    enqueue_sample_rest(s, 0, sk3_at(s, s->t));
+    s->pending = false;
+}
+
 bool sampling(const lb_sim *s) { return s->sample_every > 0; }
 
 int64_t graph_period(const lb_sim *s) {
@@ -321,36 +346,50 @@ int64_t graph_period(const lb_sim *s) {
 }
 
 void drop_graph(lb_sim *s) {
-    if (s->gexec) {
-        (void)hipGraphExecDestroy(s->gexec);
-        s->gexec = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        if (s->gexec[i]) {
+            (void)hipGraphExecDestroy(s->gexec[i]);
+            s->gexec[i] = nullptr;
+        }
+        s->g_steps[i] = 0;
     }
-    s->g_steps = 0;
 }
 
 // Capture G steps (G a multiple of the graph period) starting from an even
-// step count whose value is a multiple of the period.
-int build_graph(lb_sim *s, int G) {
-    drop_graph(s);
+// step count whose value is a multiple of the period.  The sample of a state
+// reached inside the loop is taken after the next step kernel, which writes
+// its snapshot; start_pending: the starting state's sample is due too.  The
+// last state's sample is left pending (G is a multiple of sample_every).
+int build_graph(lb_sim *s, int G, bool start_pending) {
+    const int gi = start_pending ? 1 : 0;
+    if (s->gexec[gi]) {
+        (void)hipGraphExecDestroy(s->gexec[gi]);
+        s->gexec[gi] = nullptr;
+        s->g_steps[gi] = 0;
+    }
     hipStream_t keep = s->stream;
     s->stream = s->cap_stream;
     HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
     for (int k = 0; k < G; ++k) {
-        enqueue_step(s, k & 1, k);
-        if (sampling(s) && (k + 1) % s->sample_every == 0) enqueue_sample(s, (k + 1) & 1, k + 1, sk3_at(s, k + 1));
+        const bool snap = sampling(s) && (k == 0 ? start_pending : k % s->sample_every == 0);
+        enqueue_step(s, k & 1, k, snap ? s->d_snap : nullptr);
+        if (snap) {
+            enqueue_reductions(s);
+            enqueue_sample_rest(s, k, sk3_at(s, k));
+        }
     }
     hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s->cap_stream, s->d_step, (int64_t)G);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s->cap_stream, &graph);
     s->stream = keep;
     if (e != hipSuccess) return hip_fail(e);
-    e = hipGraphInstantiate(&s->gexec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&s->gexec[gi], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        s->gexec = nullptr;
+        s->gexec[gi] = nullptr;
         return hip_fail(e);
     }
-    s->g_steps = G;
+    s->g_steps[gi] = G;
     return LB_OK;
 }
 
@@ -721,20 +760,28 @@ int lb_step(lb_sim *s, int64_t n) {
     while (n > 0) {
         const int G = s->plan.graph_steps;
         if (G > 0 && s->t % P == 0 && n >= G) {
-            if (!s->gexec || s->g_steps != G) {
-                int rc = build_graph(s, G);
+            const int gi = s->pending ? 1 : 0;
+            if (!s->gexec[gi] || s->g_steps[gi] != G) {
+                int rc = build_graph(s, G, s->pending);
                 if (rc) return rc;
             }
-            HIPCHK(hipGraphLaunch(s->gexec, s->stream));
+            HIPCHK(hipGraphLaunch(s->gexec[gi], s->stream));
             s->t += G;
             n -= G;
+            s->pending = sampling(s);
             continue;
         }
         const int cur = (int)(s->t & 1);
-        enqueue_step(s, cur, 0);
+        const bool snap = s->pending;
+        enqueue_step(s, cur, 0, snap ? s->d_snap : nullptr);
+        if (snap) {  // the sample of the state this step started from
+            enqueue_reductions(s);
+            enqueue_sample_rest(s, 0, sk3_at(s, s->t));
+            s->pending = false;
+        }
         hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s->stream, s->d_step, (int64_t)1);
         s->t += 1;
-        if (sampling(s) && s->t % s->sample_every == 0) enqueue_sample(s, cur ^ 1, 0, sk3_at(s, s->t));
+        if (sampling(s) && s->t % s->sample_every == 0) s->pending = true;
         n -= 1;
     }
     HIPCHK(hipGetLastError());
@@ -748,6 +795,7 @@ int lb_sync(lb_sim *s) {
 
 int lb_moments(lb_sim *s, int replica, lb_moments_t *out, double *sk, double *series) {
     if (!s || !out || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    flush_pending(s);
     enqueue_totals(s, (int)(s->t & 1));
     HIPCHK(hipGetLastError());
     const SampDesc &d = s->hsd[replica];
@@ -803,6 +851,7 @@ int lb_histogram(lb_sim *s, int replica, uint64_t *counts) {
     if (!s || !counts || replica < 0 || replica >= s->nrep) return LB_EINVAL;
     const SampDesc &d = s->hsd[replica];
     if (d.hist_bins <= 0) return LB_ESTATE;
+    flush_pending(s);
     const size_t n = (size_t)d.nlev * (d.hist_bins + 2);
     if (n > 0)
         HIPCHK(hipMemcpyAsync(counts, s->d_hist + d.hist_off, sizeof(uint64_t) * n, hipMemcpyDeviceToHost,
@@ -872,6 +921,7 @@ int lb_sk3_shells(lb_sim *s, int replica, int32_t *n_shells, int64_t *modes, dou
 int lb_sk3(lb_sim *s, int replica, int64_t *n_samples, double *sum_C) {
     if (!s || !n_samples || !sum_C || replica < 0 || replica >= s->nrep) return LB_EINVAL;
     if (s->sk3_stride <= 0) return LB_ESTATE;
+    flush_pending(s);
     const lb_sim::Sk3Rep &q = s->sk3[replica];
     HIPCHK(hipMemcpyAsync(sum_C, s->d_sk3_acc + q.acc_off, sizeof(double) * q.n_shells, hipMemcpyDeviceToHost,
                           s->stream));
@@ -961,6 +1011,7 @@ int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f) {
 
 int lb_set_populations(lb_sim *s, int replica, const double *f) {
     if (!s || !f || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    flush_pending(s);  // the due sample belongs to the state being replaced
     const RepDesc &d = s->hdesc[replica];
     const size_t bytes = sizeof(double) * Q * (size_t)d.N;
     double *df = (double *)dev_alloc(s, bytes);
@@ -990,6 +1041,7 @@ int lb_set_populations(lb_sim *s, int replica, const double *f) {
 
 int lb_reset_moments(lb_sim *s) {
     if (!s) return LB_EINVAL;
+    flush_pending(s);  // a due sample belongs to the period being discarded
     HIPCHK(hipMemsetAsync(s->d_acc, 0, sizeof(double) * std::max<int64_t>(s->acc_len, 1), s->stream));
     HIPCHK(hipMemsetAsync(s->d_series, 0, sizeof(double) * std::max<int64_t>(s->series_len, 1), s->stream));
     HIPCHK(hipMemsetAsync(s->d_nsamp, 0, sizeof(int64_t) * s->nrep, s->stream));
@@ -1071,8 +1123,10 @@ int lb_tune(lb_sim *s, int steps, lb_plan *best) {
             c.graph_steps = g ? gsteps : 0;
             if (lb_set_plan(s, &c) != LB_OK) break;
             // align to the graph period, warm up (and capture)
+            // (two graph replays: the loops with and without a sample pending at
+            // their start are both captured before the timed replay)
             int64_t align = (P - s->t % P) % P;
-            if ((rc = lb_step(s, align + (g ? gsteps : 1)))) break;
+            if ((rc = lb_step(s, align + (g ? 2 * gsteps : 1)))) break;
             if ((rc = hip_fail(hipEventRecord(e0, s->stream)))) break;
             if ((rc = lb_step(s, g ? gsteps : steps))) break;
             if ((rc = hip_fail(hipEventRecord(e1, s->stream)))) break;

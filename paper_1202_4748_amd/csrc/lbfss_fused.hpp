@@ -98,7 +98,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nt) {
 template <typename T, int TX, int TY, bool RING>
 __global__ void __launch_bounds__(TX * TY)
 k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const T *__restrict__ pop,
-        T *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err) {
+        T *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err,
+        float *__restrict__ snap, int64_t total) {
     constexpr int EX = TX + 4, EP = EX * (TY + 4);
     constexpr int MX = TX + 2, MP = MX * (TY + 2);
     __shared__ float s_rho[5][EP];
@@ -256,6 +257,7 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
             }
             const uint32_t s = site_c + (uint32_t)z * LL;
             const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
+            if (snap) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
             const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
             bad |= !(rho > 0.0f && rho < 1e30f);  // Sec. III B: rho must stay positive
             T *oz = obase + (uint32_t)z * LL;
@@ -310,7 +312,8 @@ __device__ __forceinline__ uint32_t pull_off(int q, const PlaneOffs &o) {
 template <int TX, int TY, bool ROWS>
 __global__ void __launch_bounds__(TX * TY)
 k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const float *__restrict__ pop,
-               float *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err) {
+               float *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err,
+        float *__restrict__ snap, int64_t total) {
     constexpr int NT = TX * TY;
     constexpr int NW = NT / 64;
     constexpr int EX = TX + 4, EP = EX * (TY + 4);
@@ -525,7 +528,8 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
                 }
                 const uint32_t s = site_c + (uint32_t)z * LL;
                 const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
-                const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
+                if (snap) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
+            const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
                 bad |= !(rho > 0.0f && rho < 1e30f);  // Sec. III B: rho must stay positive
                 float *oz = obase + (uint32_t)z * LL;
 #pragma unroll
@@ -602,16 +606,17 @@ constexpr bool kFusedRing = LBFSS_FUSED_RING;
 
 template <typename T>
 void launch_fused(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const T *in, T *out,
-                  const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream) {
+                  const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream, float *snap,
+                  int64_t total) {
     const bool ring = kFusedRing;
 #define LBFSS_LAUNCH_FUSED(TX_, TY_)                                                                          \
     do {                                                                                                     \
         if (ring)                                                                                            \
             hipLaunchKernelGGL((k_fused<T, TX_, TY_, true>), dim3(n_tiles), dim3(TX_ * TY_), 0, stream, desc, \
-                               tiles, in, out, step, koff, err);                                             \
+                               tiles, in, out, step, koff, err, snap, total);                                \
         else                                                                                                 \
             hipLaunchKernelGGL((k_fused<T, TX_, TY_, false>), dim3(n_tiles), dim3(TX_ * TY_), 0, stream,      \
-                               desc, tiles, in, out, step, koff, err);                                       \
+                               desc, tiles, in, out, step, koff, err, snap, total);                          \
     } while (0)
     if (tx == 16 && ty == 16) LBFSS_LAUNCH_FUSED(16, 16);
     else if (tx == 16 && ty == 8) LBFSS_LAUNCH_FUSED(16, 8);
@@ -630,19 +635,20 @@ inline bool rows_tile_ok(int tx, int ty) { return staged_tile_ok(tx, ty) || (tx 
 
 template <bool ROWS>
 void launch_fused_staged(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const float *in, float *out,
-                         const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream) {
+                         const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream, float *snap,
+                         int64_t total) {
     if (tx == 16 && ty == 16)
         hipLaunchKernelGGL((k_fused_staged<16, 16, ROWS>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
-                           out, step, koff, err);
+                           out, step, koff, err, snap, total);
     else if (tx == 16 && ty == 8)
         hipLaunchKernelGGL((k_fused_staged<16, 8, ROWS>), dim3(n_tiles), dim3(128), 0, stream, desc, tiles, in,
-                           out, step, koff, err);
+                           out, step, koff, err, snap, total);
     else if (ROWS && tx == 64 && ty == 4)
         hipLaunchKernelGGL((k_fused_staged<64, 4, true>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
-                           out, step, koff, err);
+                           out, step, koff, err, snap, total);
     else
         hipLaunchKernelGGL((k_fused_staged<32, 8, ROWS>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
-                           out, step, koff, err);
+                           out, step, koff, err, snap, total);
 }
 
 }  // namespace lbfss

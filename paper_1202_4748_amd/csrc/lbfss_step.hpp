@@ -217,11 +217,25 @@ k_chem_potential(const RepDesc *__restrict__ desc, int nrep, int64_t total,
 
 // Split plan, pass 3: force, collision, noise; the post-collision values are
 // written in place of the site (pull streaming reads them next step).
+// Sample snapshot written by a step kernel: density deviation and momentum
+// of the pulled (pre-collision) populations of flattened site g, which are
+// the state the previous step left (the functions k_snapshot uses, so both
+// routes give the same bits).  Layout [4][total]: drho, jx, jy, jz.
+__device__ __forceinline__ void write_snapshot(float *__restrict__ snap, int64_t total, int64_t g,
+                                               const float (&r)[Q]) {
+    float jx, jy, jz;
+    momentum_of(r, jx, jy, jz);
+    snap[g] = drho_of(r);
+    snap[total + g] = jx;
+    snap[2 * total + g] = jy;
+    snap[3 * total + g] = jz;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T *__restrict__ pop,
           T *__restrict__ pop_out, const float *__restrict__ drho, const float *__restrict__ mu,
-          const uint64_t *__restrict__ step, int koff, int *__restrict__ err) {
+          const uint64_t *__restrict__ step, int koff, int *__restrict__ err, float *__restrict__ snap) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= total) return;
     const int r = find_rep(desc, nrep, g);
@@ -244,6 +258,7 @@ k_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T *__
     }
     float f[Q];
     pull(pop + Q * d.site_off, d.N, n, f);
+    if (snap) write_snapshot(snap, total, g, f);
     const uint64_t t = *step + (uint64_t)koff;
     const SiteNoise noise{(uint32_t)s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
     const float rho = collide_site(d, f, Fx, Fy, Fz, noise);

@@ -95,3 +95,36 @@ def test_mass_and_momentum_budget():
         assert drift < 500 * N ** 0.5 * 6e-8 / N + 1e-9
         if prm["b"] == 0.0:
             assert np.max(np.abs(m1["momentum"])) < 1e-4
+
+
+@pytest.mark.parametrize("kernel,graph", [("rows", 0), ("rows", 20), ("split", 10), ("fused", 20)])
+def test_sample_timing_does_not_change_results(kernel, graph):
+    """A sample of the state after step t is taken by the next step kernel
+    (which writes the snapshot) or, when a result is read first, by a separate
+    snapshot pass: both give the same bits.  Run A steps straight through
+    (direct launches or graph replays), run B reads moments after every step
+    so every sample is flushed; accumulators, histograms, 3D S(k) and the
+    series must agree exactly."""
+    lbf = require_gpu()
+    L = 16
+    say(f"sample timing {kernel} graph={graph}")
+    prm = dict(M0, sample_every=5, series_capacity=16, hist_bins=32, hist_range=0.05, sk3_stride=2)
+    a = lbf.Sim(L, 41, **prm)
+    b = lbf.Sim(L, 41, **prm)
+    for s_ in (a, b):
+        s_.set_plan(kernel, (16, 16, 8), graph)
+    a.step(40)
+    for _ in range(40):
+        b.step(1)
+        b.moments()
+    ma, mb = a.moments(series=True), b.moments(series=True)
+    assert ma["n_samples"] == mb["n_samples"] == 8
+    for la, lb_ in zip(ma["levels"], mb["levels"]):
+        for k in ("m", "m2", "m3", "m4", "abs_m", "E", "E2"):
+            assert la[k] == lb_[k], (la["Lb"], k)
+    assert np.array_equal(ma["sk"], mb["sk"])
+    assert np.array_equal(ma["series"], mb["series"])
+    assert np.array_equal(a.histogram(), b.histogram())
+    ka, kb = a.sk3(), b.sk3()
+    assert ka["n_samples"] == kb["n_samples"] == 4 and np.array_equal(ka["sum_C"], kb["sum_C"])
+    assert ma["series"][:, 0].tolist() == [5.0 * (i + 1) for i in range(8)]
