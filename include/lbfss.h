@@ -145,7 +145,8 @@ enum {
     LB_KERNEL_STAGED = 2, /* as FUSED, the next plane's pulls staged asynchronously in LDS
                            * (FP32 storage; FP16 handles run FUSED) */
     LB_KERNEL_ROWS = 3    /* as STAGED, the staging copies the source rows of each population
-                           * with 16-byte loads; every L a multiple of 4 (else LB_EINVAL) */
+                           * with 16-byte loads (FP32 or FP16 storage); every L a multiple
+                           * of 4 (FP32) or 8 (FP16), else LB_EINVAL */
 };
 
 typedef struct {

@@ -111,10 +111,11 @@ struct lb_sim {
 };
 
 // The rows staging copies 16-byte chunks that must not straddle the periodic
-// seam: every lattice edge a multiple of 4.
+// seam: every lattice edge a multiple of 4 (FP32) or 8 (FP16 storage).
 static bool rows_ok(const lb_sim *s) {
+    const int ch = s->storage == LB_FP16 ? 8 : 4;
     for (const auto &d : s->hdesc)
-        if (d.L % 4) return false;
+        if (d.L % ch) return false;
     return true;
 }
 
@@ -195,15 +196,15 @@ void launch_step(lb_sim *s, int cur, int koff, float *snap) {
     const T *in = (const T *)s->pop[cur];
     T *out = (T *)s->pop[cur ^ 1];
     const int64_t total = s->total_sites;
-    if ((s->plan.kernel == LB_KERNEL_STAGED || s->plan.kernel == LB_KERNEL_ROWS) && s->n_tiles > 0 &&
-        std::is_same<T, float>::value) {
-        if (s->plan.kernel == LB_KERNEL_ROWS)
-            launch_fused_staged<true>(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out, s->d_step,
-                                      koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream, snap, total);
-        else
-            launch_fused_staged<false>(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out,
-                                       s->d_step, koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream, snap,
-                                       total);
+    if (s->plan.kernel == LB_KERNEL_ROWS && s->n_tiles > 0) {
+        launch_fused_staged<T, true>(s->d_desc, s->d_tiles, s->n_tiles, in, out, s->d_step, koff, s->d_err,
+                                     s->plan.tile_x, s->plan.tile_y, s->stream, snap, total);
+        return;
+    }
+    if (s->plan.kernel == LB_KERNEL_STAGED && s->n_tiles > 0 && std::is_same<T, float>::value) {
+        launch_fused_staged<float, false>(s->d_desc, s->d_tiles, s->n_tiles, (const float *)in, (float *)out,
+                                          s->d_step, koff, s->d_err, s->plan.tile_x, s->plan.tile_y, s->stream, snap,
+                                          total);
         return;
     }
     if (s->plan.kernel != LB_KERNEL_SPLIT && s->n_tiles > 0) {
@@ -216,9 +217,14 @@ void launch_step(lb_sim *s, int cur, int koff, float *snap) {
                        s->total_sites, in, s->d_drho);
     hipLaunchKernelGGL(k_chem_potential, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
                        s->total_sites, (const float *)s->d_drho, s->d_mu);
-    hipLaunchKernelGGL(k_collide<T>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
-                       s->total_sites, in, out, (const float *)s->d_drho, (const float *)s->d_mu,
-                       (const uint64_t *)s->d_step, koff, s->d_err, snap);
+    if (snap)
+        hipLaunchKernelGGL((k_collide<T, true>), dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc,
+                           s->nrep, s->total_sites, in, out, (const float *)s->d_drho, (const float *)s->d_mu,
+                           (const uint64_t *)s->d_step, koff, s->d_err, snap);
+    else
+        hipLaunchKernelGGL((k_collide<T, false>), dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc,
+                           s->nrep, s->total_sites, in, out, (const float *)s->d_drho, (const float *)s->d_mu,
+                           (const uint64_t *)s->d_step, koff, s->d_err, snap);
 }
 
 // One step; with snap set the step kernel also writes the sample snapshot of
@@ -725,7 +731,7 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
     // default plan: the fused kernel, with rows staging where it applies
     lb_plan def{LB_KERNEL_FUSED, 32, 8, 16, 0, 0};
     default_fused_tile(s->hdesc, def.tile_x, def.tile_y, def.tile_z);
-    if (s->storage == LB_FP32 && rows_ok(s)) def.kernel = LB_KERNEL_ROWS;
+    if (rows_ok(s)) def.kernel = LB_KERNEL_ROWS;
     if (lb_set_plan(s, &def) != LB_OK) {
         lb_plan split{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0};
         if ((rc = lb_set_plan(s, &split))) return fail(rc);
@@ -1107,7 +1113,7 @@ int lb_tune(lb_sim *s, int steps, lb_plan *best) {
         cands.push_back(lb_plan{LB_KERNEL_FUSED, t[0], t[1], t[2], 0, 0});
         if (s->storage == LB_FP32 && staged_tile_ok(t[0], t[1]))
             cands.push_back(lb_plan{LB_KERNEL_STAGED, t[0], t[1], t[2], 0, 0});
-        if (s->storage == LB_FP32 && rows_tile_ok(t[0], t[1]) && rows_ok(s))
+        if (rows_tile_ok(t[0], t[1]) && rows_ok(s))
             cands.push_back(lb_plan{LB_KERNEL_ROWS, t[0], t[1], t[2], 0, 0});
     }
     const int64_t P = graph_period(s);

@@ -95,7 +95,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nt) {
     return (b & 7) * per + (b >> 3);
 }
 
-template <typename T, int TX, int TY, bool RING>
+template <typename T, int TX, int TY, bool RING, bool SNAP>
 __global__ void __launch_bounds__(TX * TY)
 k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const T *__restrict__ pop,
         T *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err,
@@ -257,7 +257,7 @@ k_fused(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, c
             }
             const uint32_t s = site_c + (uint32_t)z * LL;
             const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
-            if (snap) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
+            if constexpr (SNAP) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
             const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
             bad |= !(rho > 0.0f && rho < 1e30f);  // Sec. III B: rho must stay positive
             T *oz = obase + (uint32_t)z * LL;
@@ -309,11 +309,12 @@ __device__ __forceinline__ uint32_t pull_off(int q, const PlaneOffs &o) {
 // of 4), with 16-byte loads spread over all waves; a pulled value is then the
 // rectangle entry at the site's row and at column ex + 2 - cx_q.  The rows
 // mode issues about a quarter of the load instructions for the same data.
-template <int TX, int TY, bool ROWS>
+template <typename T, int TX, int TY, bool ROWS, bool SNAP>
 __global__ void __launch_bounds__(TX * TY)
-k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const float *__restrict__ pop,
-               float *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err,
-        float *__restrict__ snap, int64_t total) {
+k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const T *__restrict__ pop,
+               T *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err,
+               float *__restrict__ snap, int64_t total) {
+    static_assert(ROWS || sizeof(T) == 4, "the per-site staging copies whole dwords");
     constexpr int NT = TX * TY;
     constexpr int NW = NT / 64;
     constexpr int EX = TX + 4, EP = EX * (TY + 4);
@@ -324,11 +325,13 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     static_assert(NH_MAX <= NT || (ROWS && NH_MAX <= 2 * NT), "halo sites per thread");
     constexpr bool H2 = NH_MAX > NT;
     constexpr int NHW = (std::min(NH_MAX, NT) + 63) / 64;  // waves that load halo sites
-    // rows mode: source rectangle of RW floats per row, CW 16-byte chunks
-    constexpr int RW = TX + 8, CW = RW / 4, NL = CW * (TY + 4), NM = (NL + 63) / 64;
-    constexpr int NS = ROWS ? 4 * NL : NT + NHW * 64;  // staging floats per population
+    // rows mode: source rectangle of RW values per row (CH values in a 16-byte
+    // chunk, CH columns of margin each side), CW chunks per row
+    constexpr int CH = 16 / (int)sizeof(T);
+    constexpr int RW = TX + 2 * CH, CW = RW / CH, NL = CW * (TY + 4), NM = (NL + 63) / 64;
+    constexpr int NS = ROWS ? CH * NL : NT + NHW * 64;  // staged values per population
     // rings: densities of planes p - 3 .. p, potentials of p - 3 .. p - 1
-    __shared__ float s_stage[Q][NS];
+    __shared__ T s_stage[Q][NS];
     __shared__ float s_rho[4][EP];
     __shared__ float s_mu[3][MP];
 
@@ -336,8 +339,8 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     const RepDesc &d = desc[tl.rep];
     const int L = d.L;
     const uint32_t N = (uint32_t)d.N, LL = (uint32_t)(L * L);
-    const float *base = pop + Q * d.site_off;
-    float *obase = pop_out + Q * d.site_off;
+    const T *base = pop + Q * d.site_off;
+    T *obase = pop_out + Q * d.site_off;
     const uint64_t t = *step + (uint64_t)koff;
     const bool force_on = !(d.flags & 1);
 
@@ -349,7 +352,7 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     const int sx = tl.x0 + (inner ? ix : 0), sy = tl.y0 + (inner ? iy : 0);
     const uint32_t site_c = (uint32_t)(sx + sy * L);
     PlaneOffs io;
-    io.set(sx, sy, L, sizeof(float));
+    io.set(sx, sy, L, sizeof(T));
     const int r_in = (iy + 2) * EX + (ix + 2);
     const int m_in = (iy + 1) * MX + (ix + 1);
 
@@ -380,7 +383,7 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     if (has_h2) halo_pos(tid + NT, hx2, hy2);
     const int r_h2 = hy2 * EX + hx2;
     PlaneOffs ho;
-    ho.set(wrap_near(tl.x0 - 2 + hx, L), wrap_near(tl.y0 - 2 + hy, L), L, sizeof(float));
+    ho.set(wrap_near(tl.x0 - 2 + hx, L), wrap_near(tl.y0 - 2 + hy, L), L, sizeof(T));
     const int r_h = hy * EX + hx;
 
     // potential halo
@@ -421,10 +424,10 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
             const int j = m * 64 + lane;
             r_on[m] = j < NL;
             const int ey = j / CW, k = j - (j / CW) * CW;
-            r_col[m] = (uint32_t)(((tl.x0 - 4 + 4 * k) % L + L) % L) * sizeof(float);
+            r_col[m] = (uint32_t)(((tl.x0 - CH + CH * k) % L + L) % L) * sizeof(T);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                r_row[m][c] = (uint32_t)(((tl.y0 - 2 + ey - (c - 1)) % L + L) % L) * (uint32_t)L * sizeof(float);
+                r_row[m][c] = (uint32_t)(((tl.y0 - 2 + ey - (c - 1)) % L + L) % L) * (uint32_t)L * sizeof(T);
         }
     }
 
@@ -442,7 +445,7 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
                 for (int m = 0; m < NM; ++m)
                     if (r_on[m])
                         __builtin_amdgcn_global_load_lds((gptr_t)(bq + r_row[m][cy_of(q) + 1] + r_col[m]),
-                                                         (lptr_t)&s_stage[q][m * 256], 16, 0, 0);
+                                                         (lptr_t)&s_stage[q][m * 64 * CH], 16, 0, 0);
             } else {
                 __builtin_amdgcn_global_load_lds((gptr_t)(bq + pull_off(q, io)), (lptr_t)&s_stage[q][wave * 64], 4,
                                                  0, 0);
@@ -453,9 +456,10 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
         }
     };
     // LDS slot of the pulled value q of the tile site / the halo site
-    auto slot_in = [&](int q) { return ROWS ? (iy + 2) * RW + ix + 4 - cx_of(q) : tid; };
-    auto slot_h = [&](int q) { return ROWS ? hy * RW + hx + 2 - cx_of(q) : NT + tid; };
-    auto slot_h2 = [&](int q) { return hy2 * RW + hx2 + 2 - cx_of(q); };
+    // (rows: column ex + CH - 2 - cx_q of the rectangle for extended column ex)
+    auto slot_in = [&](int q) { return ROWS ? (iy + 2) * RW + ix + CH - cx_of(q) : tid; };
+    auto slot_h = [&](int q) { return ROWS ? hy * RW + hx + CH - 2 - cx_of(q) : NT + tid; };
+    auto slot_h2 = [&](int q) { return hy2 * RW + hx2 + CH - 2 - cx_of(q); };
 
     bool bad = false;
     float A[Q], B[Q], C[Q];
@@ -471,19 +475,19 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
             float *rs = s_rho[(p + 8) & 3];
             if (inner) {
 #pragma unroll
-                for (int q = 0; q < Q; ++q) ld[q] = s_stage[q][slot_in(q)];
+                for (int q = 0; q < Q; ++q) ld[q] = Store<T>::ld(s_stage[q], slot_in(q));
                 rs[r_in] = drho_of(ld);
             }
             if (has_h) {
                 float h[Q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) h[q] = s_stage[q][slot_h(q)];
+                for (int q = 0; q < Q; ++q) h[q] = Store<T>::ld(s_stage[q], slot_h(q));
                 rs[r_h] = drho_of(h);
             }
             if (H2 && has_h2) {
                 float h[Q];
 #pragma unroll
-                for (int q = 0; q < Q; ++q) h[q] = s_stage[q][slot_h2(q)];
+                for (int q = 0; q < Q; ++q) h[q] = Store<T>::ld(s_stage[q], slot_h2(q));
                 rs[r_h2] = drho_of(h);
             }
         }
@@ -528,10 +532,10 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
                 }
                 const uint32_t s = site_c + (uint32_t)z * LL;
                 const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
-                if (snap) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
-            const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
+                if constexpr (SNAP) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
+                const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
                 bad |= !(rho > 0.0f && rho < 1e30f);  // Sec. III B: rho must stay positive
-                float *oz = obase + (uint32_t)z * LL;
+                T *oz = obase + (uint32_t)z * LL;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) stb(oz + (size_t)q * N, io.c, cl[q]);
             }
@@ -604,25 +608,28 @@ inline std::vector<std::array<int, 3>> fused_tile_candidates(const std::vector<R
 #endif
 constexpr bool kFusedRing = LBFSS_FUSED_RING;
 
-template <typename T>
-void launch_fused(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const T *in, T *out,
-                  const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream, float *snap,
-                  int64_t total) {
-    const bool ring = kFusedRing;
-#define LBFSS_LAUNCH_FUSED(TX_, TY_)                                                                          \
-    do {                                                                                                     \
-        if (ring)                                                                                            \
-            hipLaunchKernelGGL((k_fused<T, TX_, TY_, true>), dim3(n_tiles), dim3(TX_ * TY_), 0, stream, desc, \
-                               tiles, in, out, step, koff, err, snap, total);                                \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_fused<T, TX_, TY_, false>), dim3(n_tiles), dim3(TX_ * TY_), 0, stream,      \
-                               desc, tiles, in, out, step, koff, err, snap, total);                          \
-    } while (0)
+template <typename T, bool SNAP>
+void launch_fused_snap(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const T *in, T *out,
+                       const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream, float *snap,
+                       int64_t total) {
+#define LBFSS_LAUNCH_FUSED(TX_, TY_)                                                                             \
+    hipLaunchKernelGGL((k_fused<T, TX_, TY_, kFusedRing, SNAP>), dim3(n_tiles), dim3(TX_ * TY_), 0, stream, desc, \
+                       tiles, in, out, step, koff, err, snap, total)
     if (tx == 16 && ty == 16) LBFSS_LAUNCH_FUSED(16, 16);
     else if (tx == 16 && ty == 8) LBFSS_LAUNCH_FUSED(16, 8);
     else if (tx == 64 && ty == 4) LBFSS_LAUNCH_FUSED(64, 4);
     else LBFSS_LAUNCH_FUSED(32, 8);
 #undef LBFSS_LAUNCH_FUSED
+}
+
+// snap: where the step also writes the sample snapshot of its input state,
+// or null (a separate instance without the snapshot's registers)
+template <typename T>
+void launch_fused(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const T *in, T *out,
+                  const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream, float *snap,
+                  int64_t total) {
+    if (snap) launch_fused_snap<T, true>(desc, tiles, n_tiles, in, out, step, koff, err, tx, ty, stream, snap, total);
+    else launch_fused_snap<T, false>(desc, tiles, n_tiles, in, out, step, koff, err, tx, ty, stream, snap, total);
 }
 
 inline bool staged_tile_ok(int tx, int ty) {
@@ -633,22 +640,33 @@ inline bool staged_tile_ok(int tx, int ty) {
 inline bool rows_tile_ok(int tx, int ty) { return staged_tile_ok(tx, ty) || (tx == 64 && ty == 4); }
 
 
-template <bool ROWS>
-void launch_fused_staged(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const float *in, float *out,
+template <typename T, bool ROWS, bool SNAP>
+void launch_staged_snap(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const T *in, T *out,
+                        const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream, float *snap,
+                        int64_t total) {
+    if (tx == 16 && ty == 16)
+        hipLaunchKernelGGL((k_fused_staged<T, 16, 16, ROWS, SNAP>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles,
+                           in, out, step, koff, err, snap, total);
+    else if (tx == 16 && ty == 8)
+        hipLaunchKernelGGL((k_fused_staged<T, 16, 8, ROWS, SNAP>), dim3(n_tiles), dim3(128), 0, stream, desc, tiles,
+                           in, out, step, koff, err, snap, total);
+    else if (ROWS && tx == 64 && ty == 4)
+        hipLaunchKernelGGL((k_fused_staged<T, 64, 4, true, SNAP>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles,
+                           in, out, step, koff, err, snap, total);
+    else
+        hipLaunchKernelGGL((k_fused_staged<T, 32, 8, ROWS, SNAP>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles,
+                           in, out, step, koff, err, snap, total);
+}
+
+template <typename T, bool ROWS>
+void launch_fused_staged(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const T *in, T *out,
                          const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream, float *snap,
                          int64_t total) {
-    if (tx == 16 && ty == 16)
-        hipLaunchKernelGGL((k_fused_staged<16, 16, ROWS>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
-                           out, step, koff, err, snap, total);
-    else if (tx == 16 && ty == 8)
-        hipLaunchKernelGGL((k_fused_staged<16, 8, ROWS>), dim3(n_tiles), dim3(128), 0, stream, desc, tiles, in,
-                           out, step, koff, err, snap, total);
-    else if (ROWS && tx == 64 && ty == 4)
-        hipLaunchKernelGGL((k_fused_staged<64, 4, true>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
-                           out, step, koff, err, snap, total);
+    if (snap)
+        launch_staged_snap<T, ROWS, true>(desc, tiles, n_tiles, in, out, step, koff, err, tx, ty, stream, snap, total);
     else
-        hipLaunchKernelGGL((k_fused_staged<32, 8, ROWS>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in,
-                           out, step, koff, err, snap, total);
+        launch_staged_snap<T, ROWS, false>(desc, tiles, n_tiles, in, out, step, koff, err, tx, ty, stream, snap,
+                                           total);
 }
 
 }  // namespace lbfss

@@ -231,7 +231,7 @@ __device__ __forceinline__ void write_snapshot(float *__restrict__ snap, int64_t
     snap[3 * total + g] = jz;
 }
 
-template <typename T>
+template <typename T, bool SNAP>
 __global__ void __launch_bounds__(kBlock)
 k_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T *__restrict__ pop,
           T *__restrict__ pop_out, const float *__restrict__ drho, const float *__restrict__ mu,
@@ -258,7 +258,7 @@ k_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T *__
     }
     float f[Q];
     pull(pop + Q * d.site_off, d.N, n, f);
-    if (snap) write_snapshot(snap, total, g, f);
+    if constexpr (SNAP) write_snapshot(snap, total, g, f);
     const uint64_t t = *step + (uint64_t)koff;
     const SiteNoise noise{(uint32_t)s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
     const float rho = collide_site(d, f, Fx, Fy, Fz, noise);

@@ -114,10 +114,12 @@ def test_force_off_ideal_gas():
     _compare(sim, orc, TOL32, "force off")
 
 
-def test_fp16_storage():
+@pytest.mark.parametrize("kernel", ["split", "rows"])
+def test_fp16_storage(kernel):
     lbf = require_gpu()
-    say("fp16 L=16")
+    say(f"fp16 L=16 {kernel}")
     sim = lbf.Sim(16, workloads.SEED, storage="fp16", **M0)
+    sim.set_plan(kernel, (32, 8, 5))
     orc = oracle.Sim(16, workloads.SEED, **M0)
     worst = (0.0, 0.0, 0.0)
     for t in range(100):
@@ -144,6 +146,25 @@ def test_plans_bit_identical():
         sim = lbf.Sim(L, 11, **M0)
         sim.set_plan(kernel, tile, g)
         sim.step(13)
+        states.append(sim.fields(f=True)["f"])
+    for s in states[1:]:
+        assert np.array_equal(s, states[0])
+
+
+@pytest.mark.parametrize("L", [8, 24, 40])
+def test_fp16_plans_bit_identical(L):
+    """FP16 storage: split, the register-ring fused kernel and the rows
+    staging (8-half chunks) give the same bits, with partial tiles (L = 40
+    against 32- and 64-wide tiles) and the source rows wrapping on L = 8."""
+    lbf = require_gpu()
+    say(f"fp16 plans L={L}")
+    states = []
+    for kernel, tile, g in [("split", (0, 0, 0), 0), ("fused", (32, 8, 7), 0), ("fused", (64, 4, 5), 3),
+                            ("rows", (32, 8, 7), 0), ("rows", (64, 4, 9), 0), ("rows", (16, 16, 5), 4),
+                            ("rows", (16, 8, 3), 0)]:
+        sim = lbf.Sim(L, 21, storage="fp16", **M0)
+        sim.set_plan(kernel, tile, g)
+        sim.step(9)
         states.append(sim.fields(f=True)["f"])
     for s in states[1:]:
         assert np.array_equal(s, states[0])
@@ -204,7 +225,8 @@ def test_unstable_flag_is_sticky():
 
 def test_rows_plan_needs_multiple_of_four():
     """The rows staging copies 16-byte chunks, so a lattice edge that is not a
-    multiple of 4 is refused with LB_EINVAL and the plan stays as it was."""
+    multiple of 4 (FP32) or 8 (FP16) is refused with LB_EINVAL and the plan
+    stays as it was."""
     lbf = require_gpu()
     sim = lbf.Sim(10, 1, **M0)
     before = sim.plan()
@@ -212,6 +234,13 @@ def test_rows_plan_needs_multiple_of_four():
         sim.set_plan("rows", (32, 8, 4))
     assert e.value.code == lbf.LB_EINVAL
     assert sim.plan() == before
+    # FP16 chunks hold 8 halves: L = 12 passes the FP32 rule but not this one
+    h = lbf.Sim(12, 1, storage="fp16", **M0)
+    before = h.plan()
+    with pytest.raises(lbf.LBError) as e:
+        h.set_plan("rows", (32, 8, 4))
+    assert e.value.code == lbf.LB_EINVAL
+    assert h.plan() == before
 
 
 @pytest.mark.parametrize("kernel", ["split", "rows"])
