@@ -21,6 +21,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 Arrays are flat, site = x + S*(y + S*z); reshaped to [z, y, x].
 """
+import math
+
 import numpy as np
 
 MOMENT_KEYS = ("m", "m2", "m3", "m4", "abs_m", "E", "E2")
@@ -175,6 +177,8 @@ def hist_estimates(counts, h, Lb, kT, n, sum_m, sum_m2, sum_abs_m, d=3):
                    the other Gaussian neglected
       chi_var    = L^d (<m^2> - <m>^2) / kT        Eq. (chiL)
       chi_var_low = L^d (<m^2> - <|m|>^2) / kT     Eq. (chiL-lowT)
+      m_fit, chi_fit  a Gaussian fitted to the fullest peak (gauss_fit_peak):
+                   |its centre| and L^d s^2 / kT
     A zero denominator (an empty bin, kT = 0) gives +inf."""
     counts = np.asarray(counts, dtype=np.float64)
     bins = counts.size - 2
@@ -194,9 +198,50 @@ def hist_estimates(counts, h, Lb, kT, n, sum_m, sum_m2, sum_abs_m, d=3):
     def ratio(num, den):  # an empty centre (den = 0) gives an infinite estimate
         return num / den if den > 0 else float("inf")
 
+    mu, s2 = gauss_fit_peak(counts[:bins], h)
+    chi_fit = ratio(vol * s2, kT) if np.isfinite(s2) else float("nan")
     return {"P0": P0, "chi_center": ratio(vol, 2.0 * np.pi * kT * P0 ** 2),
             "m_max": m_max, "P_max": Pmax, "chi_peak": ratio(vol, 8.0 * np.pi * kT * Pmax ** 2),
-            "chi_var": ratio(vol * (mean2 - mean ** 2), kT), "chi_var_low": ratio(vol * (mean2 - mabs ** 2), kT)}
+            "chi_var": ratio(vol * (mean2 - mean ** 2), kT), "chi_var_low": ratio(vol * (mean2 - mabs ** 2), kT),
+            "m_fit": abs(mu), "chi_fit": chi_fit}
+
+
+FIT_LEVEL = math.exp(-2.0)   # window edge: a Gaussian falls to this at +-2 s
+
+
+def gauss_fit_peak(counts, h):
+    """A Gaussian fitted to the fullest peak of a histogram (the in-range
+    bins of box_histogram over [-h, h)), Sec. IV C: the contiguous bins
+    around the fullest one (lowest index on ties) that hold at least
+    exp(-2) of its count (about +-2 standard deviations, so the region
+    between two peaks stays out) give ln(count) = c0 + c1 u + c2 u^2 by
+    least squares weighted with the counts (the inverse variance of ln of a
+    Poisson count), u = bin index - fullest index.  Centre mu = centre of
+    the fullest bin - w c1 / (2 c2); variance s^2 = -w^2 / (2 c2) - w^2 / 12,
+    the last term Sheppard's correction for counts grouped in bins of width
+    w.  Returns (mu, s^2), or (nan, nan) when fewer than three bins qualify
+    or the fitted curvature is not negative."""
+    c = np.asarray(counts, dtype=np.float64)
+    bins = c.size
+    w = 2.0 * h / bins
+    k0 = int(np.argmax(c))
+    thr = c[k0] * FIT_LEVEL
+    lo = k0
+    while lo > 0 and c[lo - 1] >= thr:
+        lo -= 1
+    hi = k0
+    while hi < bins - 1 and c[hi + 1] >= thr:
+        hi += 1
+    if hi - lo + 1 < 3:
+        return float("nan"), float("nan")
+    u = np.arange(lo, hi + 1, dtype=np.float64) - k0
+    sw = np.sqrt(c[lo:hi + 1])
+    A = np.stack([np.ones_like(u), u, u * u], axis=1) * sw[:, None]
+    coef = np.linalg.lstsq(A, np.log(c[lo:hi + 1]) * sw, rcond=None)[0]
+    if not coef[2] < 0:
+        return float("nan"), float("nan")
+    mu = -h + (k0 + 0.5) * w - w * coef[1] / (2.0 * coef[2])
+    return mu, -w * w / (2.0 * coef[2]) - w * w / 12.0
 
 
 class Accumulator:

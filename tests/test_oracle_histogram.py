@@ -110,3 +110,86 @@ def test_accumulator_histogram_counts_every_box():
     flat.add(np.full(S ** 3, 1.25))
     for L in flat.levels:
         assert flat.hist[L][8] == (S // L) ** 3
+
+
+@pytest.mark.parametrize("w_over_s", [0.05, 0.1, 0.2])
+def test_gauss_fit_recovers_chi_of_binned_gaussian(w_over_s):
+    """Exact bin probabilities of a Gaussian: the fitted variance, with
+    Sheppard's w^2/12 taken off, is the Gaussian's to O((w/s)^4); without
+    the correction it would be off by (w/s)^2 / 12 (2e-4 to 3.3e-3)."""
+    Lb, kT, chi = 4, 1e-4, 7.5
+    sigma = math.sqrt(kT * chi / Lb ** 3)
+    bins = 2 * int(round(5.0 / w_over_s)) + 1
+    h = 0.5 * bins * w_over_s * sigma
+    edges = np.linspace(-h, h, bins + 1)
+    c = _counts_from_density(_gauss_bin_probs(edges, 0.0, sigma), 1e15)
+    est = M.hist_estimates(c, h, Lb, kT, n=1.0, sum_m=0.0, sum_m2=sigma ** 2, sum_abs_m=0.0)
+    assert abs(est["chi_fit"] / chi - 1) < 0.05 * w_over_s ** 2 / 12
+    assert est["m_fit"] < 1e-6 * sigma
+
+
+def test_gauss_fit_finds_an_off_centre_peak():
+    """A peak centred 0.37 bin widths off a bin centre: the fit's centre is
+    the Gaussian's, not the bin's."""
+    Lb, kT, chi = 2, 1e-4, 2.0
+    sigma = math.sqrt(kT * chi / Lb ** 3)
+    bins, h = 400, 0.02
+    w = 2 * h / bins
+    mu = -h + (260 + 0.5) * w + 0.37 * w
+    edges = np.linspace(-h, h, bins + 1)
+    c = _counts_from_density(_gauss_bin_probs(edges, mu, sigma), 1e15)
+    got_mu, s2 = M.gauss_fit_peak(c[:bins], h)
+    assert abs(got_mu - mu) < 1e-4 * w
+    assert abs(s2 / sigma ** 2 - 1) < 1e-4
+
+
+def test_gauss_fit_two_peaks_with_interfacial_plateau():
+    """Eq. (PL-lowT) plus a flat interfacial density between the peaks
+    (1e-3 of the peak height, as in the coexistence regime, over
+    |m| < M_L - 3 s): fitting the fullest peak recovers chi and M_L, while
+    the peak height, normalised by every value, is biased by the plateau's
+    share."""
+    Lb, kT, chi, ML = 2, 1e-4, 3.0, 0.05
+    sigma = math.sqrt(kT * chi / Lb ** 3)
+    h, bins = 0.1, 1600
+    edges = np.linspace(-h, h, bins + 1)
+    p = 0.5 * (_gauss_bin_probs(edges, ML, sigma) + _gauss_bin_probs(edges, -ML, sigma))
+    w = 2 * h / bins
+    centres = edges[:-1] + 0.5 * w
+    plateau = np.where(np.abs(centres) < ML - 3 * sigma, 1e-3 * p.max(), 0.0)
+    c = _counts_from_density(p + plateau, 1e15)
+    est = M.hist_estimates(c, h, Lb, kT, n=1.0, sum_m=0.0, sum_m2=ML ** 2 + sigma ** 2, sum_abs_m=ML)
+    assert abs(est["m_fit"] - ML) < 1e-3 * w
+    assert abs(est["chi_fit"] / chi - 1) < 1e-3
+    share = plateau.sum() / (p + plateau).sum()
+    assert abs(est["chi_peak"] / chi - (1 + share) ** 2) < 2e-3
+
+
+def test_gauss_fit_of_sampled_gaussian():
+    """Sampled values (Poisson counts): the count-weighted fit recovers chi
+    within its statistical error (4e6 values, ~30 bins in the window:
+    about 0.1% on s^2; tolerance 1%)."""
+    rng = np.random.default_rng(11)
+    Lb, kT, chi = 2, 1e-4, 1.7
+    sigma = math.sqrt(kT * chi / Lb ** 3)
+    m = rng.normal(0.3 * sigma, sigma, 4_000_000)
+    h, bins = 8 * sigma, 121
+    c = M.box_histogram(m, bins, h)
+    est = M.hist_estimates(c, h, Lb, kT, n=m.size, sum_m=m.sum(), sum_m2=(m * m).sum(), sum_abs_m=np.abs(m).sum())
+    assert abs(est["chi_fit"] / chi - 1) < 0.01
+    assert abs(est["m_fit"] - 0.3 * sigma) < 0.01 * sigma
+
+
+def test_gauss_fit_degenerate_cases():
+    """One filled bin (fewer than three in the window) and a histogram
+    rising towards its edges (no peak: curvature not negative) have no fit."""
+    one = np.zeros(12)
+    one[5] = 1000
+    mu, s2 = M.gauss_fit_peak(one, 1.0)
+    assert math.isnan(mu) and math.isnan(s2)
+    u = np.arange(20) - 9.5
+    cup = np.rint(1000 * np.exp(0.01 * u * u))
+    mu, s2 = M.gauss_fit_peak(cup, 1.0)
+    assert math.isnan(s2)
+    est = M.hist_estimates(np.concatenate([one, [0, 0]]), 1.0, 2, 1e-4, 1.0, 0.0, 1e-4, 0.0)
+    assert math.isnan(est["chi_fit"])
