@@ -211,6 +211,13 @@ typedef struct {
     double chi_peak;     /* L_b^3 / (8 pi kT P_max^2): Eq. (PL-lowT) at m = M_L (Sec. IV C) */
     double chi_var;      /* L_b^3 (<m^2> - <m>^2) / kT: Eq. (chiL), from the moment sums */
     double chi_var_low;  /* L_b^3 (<m^2> - <|m|>^2) / kT: Eq. (chiL-lowT) */
+    double m_fit;        /* |centre| of a Gaussian fitted to the fullest peak (Sec. IV C):
+                          * weighted least squares of ln(count) against a quadratic in m
+                          * over the contiguous bins around the fullest one holding at
+                          * least exp(-2) of its count, weights = counts */
+    double chi_fit;      /* L_b^3 s^2 / kT, s^2 the fitted variance less w^2 / 12
+                          * (Sheppard's correction for bins of width w); NaN (and m_fit
+                          * NaN) when fewer than 3 bins qualify or the curvature is >= 0 */
 } lb_hist_est;           /* a zero denominator (empty bin, kT = 0) gives +inf */
 
 /* Susceptibility estimates of every level of a replica from its histogram and

@@ -56,7 +56,8 @@ class OzT(ctypes.Structure):
 class HistEst(ctypes.Structure):
     _fields_ = [("Lb", ctypes.c_int32), ("reserved", ctypes.c_int32), ("P0", ctypes.c_double),
                 ("chi_center", ctypes.c_double), ("m_max", ctypes.c_double), ("P_max", ctypes.c_double),
-                ("chi_peak", ctypes.c_double), ("chi_var", ctypes.c_double), ("chi_var_low", ctypes.c_double)]
+                ("chi_peak", ctypes.c_double), ("chi_var", ctypes.c_double), ("chi_var_low", ctypes.c_double),
+                ("m_fit", ctypes.c_double), ("chi_fit", ctypes.c_double)]
 
 
 class LevelSums(ctypes.Structure):

@@ -868,6 +868,55 @@ int lb_histogram(lb_sim *s, int replica, uint64_t *counts) {
 
 // Estimates of Sec. II B-C and IV C from the counts and the moment sums; an
 // empty denominator gives +inf.
+// Gaussian fitted to the fullest peak of nb in-range bins over [-h, h):
+// window = contiguous bins around the fullest (lowest index on ties) with
+// count >= exp(-2) of its count; ln(count) = c0 + c1 u + c2 u^2 by least
+// squares weighted with the counts, u = bin - fullest bin; centre and
+// variance (less w^2/12 for the binning) in *mu, *s2, NaN without a fit.
+static void gauss_fit_peak(const uint64_t *c, int nb, double h, double *mu, double *s2) {
+    *mu = *s2 = NAN;
+    const double w = 2.0 * h / nb;
+    int k0 = 0;
+    for (int k = 1; k < nb; ++k)
+        if (c[k] > c[k0]) k0 = k;
+    const double thr = (double)c[k0] * std::exp(-2.0);
+    int lo = k0, hi = k0;
+    while (lo > 0 && (double)c[lo - 1] >= thr) --lo;
+    while (hi < nb - 1 && (double)c[hi + 1] >= thr) ++hi;
+    if (hi - lo + 1 < 3) return;
+    // normal equations: sum wt u^(i+j) x_j = sum wt y u^i, i, j = 0..2
+    double S[5] = {0, 0, 0, 0, 0}, T[3] = {0, 0, 0};
+    for (int k = lo; k <= hi; ++k) {
+        const double wt = (double)c[k], u = (double)(k - k0), y = std::log((double)c[k]);
+        double p = wt;
+        for (int e = 0; e < 5; ++e, p *= u) {
+            S[e] += p;
+            if (e < 3) T[e] += p * y;
+        }
+    }
+    double A[3][4] = {{S[0], S[1], S[2], T[0]}, {S[1], S[2], S[3], T[1]}, {S[2], S[3], S[4], T[2]}};
+    for (int col = 0; col < 3; ++col) {  // Gaussian elimination with partial pivoting
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
+        if (A[piv][col] == 0.0) return;
+        for (int j = 0; j < 4; ++j) std::swap(A[col][j], A[piv][j]);
+        for (int r = col + 1; r < 3; ++r) {
+            const double f = A[r][col] / A[col][col];
+            for (int j = col; j < 4; ++j) A[r][j] -= f * A[col][j];
+        }
+    }
+    double x[3];
+    for (int r = 2; r >= 0; --r) {
+        double v = A[r][3];
+        for (int j = r + 1; j < 3; ++j) v -= A[r][j] * x[j];
+        x[r] = v / A[r][r];
+    }
+    if (!(x[2] < 0.0)) return;
+    *mu = -h + (k0 + 0.5) * w - w * x[1] / (2.0 * x[2]);
+    *s2 = -w * w / (2.0 * x[2]) - w * w / 12.0;
+}
+
 int lb_hist_estimates(lb_sim *s, int replica, lb_hist_est *out) {
     if (!s || !out || replica < 0 || replica >= s->nrep) return LB_EINVAL;
     const SampDesc &d = s->hsd[replica];
@@ -907,6 +956,10 @@ int lb_hist_estimates(lb_sim *s, int replica, lb_hist_est *out) {
         e.chi_peak = ratio(vol, 8.0 * pi * kT * Pmax * Pmax);
         e.chi_var = ratio(vol * (mean2 - mean * mean), kT);
         e.chi_var_low = ratio(vol * (mean2 - mabs * mabs), kT);
+        double mu, s2;
+        gauss_fit_peak(c, nb, h, &mu, &s2);
+        e.m_fit = std::fabs(mu);
+        e.chi_fit = std::isfinite(s2) ? ratio(vol * s2, kT) : (double)NAN;
     }
     return LB_OK;
 }
