@@ -731,7 +731,17 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
     // default plan: the fused kernel, with rows staging where it applies
     lb_plan def{LB_KERNEL_FUSED, 32, 8, 16, 0, 0};
     default_fused_tile(s->hdesc, def.tile_x, def.tile_y, def.tile_z);
-    if (rows_ok(s)) def.kernel = LB_KERNEL_ROWS;
+    if (rows_ok(s)) {
+        def.kernel = LB_KERNEL_ROWS;
+        // FP16 rows: 64 x 4 tiles (four workgroups per CU, wider source rows)
+        // on large lattices, where 32 x 8 measures about 10% slower
+        int maxL = 0;
+        for (const auto &d : s->hdesc) maxL = std::max(maxL, d.L);
+        if (s->storage == LB_FP16 && maxL >= 128) {
+            def.tile_x = 64;
+            def.tile_y = 4;
+        }
+    }
     if (lb_set_plan(s, &def) != LB_OK) {
         lb_plan split{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0};
         if ((rc = lb_set_plan(s, &split))) return fail(rc);

@@ -56,9 +56,15 @@ template <typename T>
 __device__ __forceinline__ float ldb(const T *p, uint32_t boff) {
     return Store<T>::ld((const T *)((const char *)p + boff), 0);
 }
+// Store of a post-collision value: non-temporal, so the written planes do
+// not push out of L2 the source rows that neighbouring tiles still read as
+// their halo (the next step reads these values, long after L2 turned over).
 template <typename T>
 __device__ __forceinline__ void stb(T *p, uint32_t boff, float v) {
-    Store<T>::st((T *)((char *)p + boff), 0, v);
+    if constexpr (sizeof(T) == 4)
+        __builtin_nontemporal_store(v, (float *)((char *)p + boff));
+    else
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), (unsigned short *)((char *)p + boff));
 }
 
 // Pull of the 19 populations of a site of plane z: buf_q(x - c_q).  qz[q] is
@@ -330,10 +336,14 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     constexpr int CH = 16 / (int)sizeof(T);
     constexpr int RW = TX + 2 * CH, CW = RW / CH, NL = CW * (TY + 4), NM = (NL + 63) / 64;
     constexpr int NS = ROWS ? CH * NL : NT + NHW * 64;  // staged values per population
-    // rings: densities of planes p - 3 .. p, potentials of p - 3 .. p - 1
+    // rings: densities of planes p - 2 .. p, potentials of p - 2 .. p - 1;
+    // what the collision of plane z needs from plane z - 1 is taken into
+    // registers one iteration earlier (psi_m), so those planes can go
     __shared__ T s_stage[Q][NS];
-    __shared__ float s_rho[4][EP];
-    __shared__ float s_mu[3][MP];
+    __shared__ float s_rho[3][EP];
+    __shared__ float s_mu[2][MP];
+    auto rslot = [](int p) { return (p + 9) % 3; };  // p >= -2
+    auto mslot = [](int p) { return (p + 8) & 1; };
 
     const FusedTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
     const RepDesc &d = desc[tl.rep];
@@ -461,6 +471,13 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     auto slot_h = [&](int q) { return ROWS ? hy * RW + hx + CH - 2 - cx_of(q) : NT + tid; };
     auto slot_h2 = [&](int q) { return hy2 * RW + hx2 + CH - 2 - cx_of(q); };
 
+    // psi(y) = drho(y) / 3 - rho(x) mu(y), the force's summand (one
+    // expression for every use, so every plan rounds alike)
+    auto psi = [](float dr, float rho_x, float mu) { return (1.0f / 3.0f) * dr - rho_x * mu; };
+    // psi at the five neighbours in plane z - 1 of the next collision's site:
+    // (0,0), (-1,0), (1,0), (0,-1), (0,1) in x, y
+    float psi_m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+
     bool bad = false;
     float A[Q], B[Q], C[Q];
     bool stored_last = false;  // did the previous iteration issue stores (wave-uniform)
@@ -472,7 +489,7 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
         else __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt == 0
         __syncthreads();
         {
-            float *rs = s_rho[(p + 8) & 3];
+            float *rs = s_rho[rslot(p)];
             if (inner) {
 #pragma unroll
                 for (int q = 0; q < Q; ++q) ld[q] = Store<T>::ld(s_stage[q], slot_in(q));
@@ -496,8 +513,8 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
         if (p + 1 <= tl.z0 + tl.nz + 1) issue(p + 1);
         // 3. chemical potential of plane p - 1
         if (p - 1 >= tl.z0 - 1) {
-            const float *r0 = s_rho[(p - 2 + 8) & 3], *r1 = s_rho[(p - 1 + 8) & 3], *r2 = s_rho[(p + 8) & 3];
-            float *ms = s_mu[(p - 1 + 9) % 3];
+            const float *r0 = s_rho[rslot(p - 2)], *r1 = s_rho[rslot(p - 1)], *r2 = s_rho[rslot(p)];
+            float *ms = s_mu[mslot(p - 1)];
             auto mu_at = [&](int ri) {
                 const float c = r1[ri];
                 return chem_potential(d, c, lap18(c, [&](int dx, int dy, int dz) {
@@ -517,14 +534,14 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
                 const int z = p - 2;
                 float Fx = 0.f, Fy = 0.f, Fz = 0.f;
                 if (force_on) {
-                    const float *rm = s_rho[(z - 1 + 8) & 3], *rc = s_rho[(z + 8) & 3],
-                                *rp = s_rho[(z + 1 + 8) & 3];
-                    const float *mm = s_mu[(z - 1 + 9) % 3], *mc = s_mu[(z + 9) % 3], *mp = s_mu[(z + 1 + 9) % 3];
+                    const float *rc = s_rho[rslot(z)], *rp = s_rho[rslot(z + 1)];
+                    const float *mc = s_mu[mslot(z)], *mp = s_mu[mslot(z + 1)];
                     const float rho_x = d.rho_c + rc[r_in];
                     const Grad18 gr = grad18([&](int dx, int dy, int dz) {
-                        const float *rr = dz < 0 ? rm : (dz > 0 ? rp : rc);
-                        const float *mu = dz < 0 ? mm : (dz > 0 ? mp : mc);
-                        return (1.0f / 3.0f) * rr[r_in + dy * EX + dx] - rho_x * mu[m_in + dy * MX + dx];
+                        if (dz < 0) return psi_m[dy == 0 ? (dx == 0 ? 0 : (dx < 0 ? 1 : 2)) : (dy < 0 ? 3 : 4)];
+                        const float *rr = dz > 0 ? rp : rc;
+                        const float *mu = dz > 0 ? mp : mc;
+                        return psi(rr[r_in + dy * EX + dx], rho_x, mu[m_in + dy * MX + dx]);
                     });
                     Fx = gr.gx;
                     Fy = gr.gy;
@@ -539,6 +556,17 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
 #pragma unroll
                 for (int q = 0; q < Q; ++q) stb(oz + (size_t)q * N, io.c, cl[q]);
             }
+        }
+        // 5. plane p - 2 seen from the next collision (plane p - 1), before
+        //    the next iteration overwrites it
+        if (force_on && inner && p - 1 >= tl.z0 && p - 1 < tl.z0 + tl.nz) {
+            const float *rz = s_rho[rslot(p - 2)], *mz = s_mu[mslot(p - 2)];
+            const float rho_n = d.rho_c + s_rho[rslot(p - 1)][r_in];
+            psi_m[0] = psi(rz[r_in], rho_n, mz[m_in]);
+            psi_m[1] = psi(rz[r_in - 1], rho_n, mz[m_in - 1]);
+            psi_m[2] = psi(rz[r_in + 1], rho_n, mz[m_in + 1]);
+            psi_m[3] = psi(rz[r_in - EX], rho_n, mz[m_in - MX]);
+            psi_m[4] = psi(rz[r_in + EX], rho_n, mz[m_in + MX]);
         }
     };
 
