@@ -51,16 +51,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kname, workload, storage):
+def read_traffic(kname, workload, storage, plan):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary, or None if absent or taken on other kernel sources."""
+    counter summary, or None if absent, taken on other kernel sources or on
+    another kernel or tile (plan: the plan dict being timed)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kname}_{workload}_{storage}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
     b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b or m.group(1) != kernel_source_hash():
+    t = re.search(r"plan (\w+):(\d+):(\d+):(\d+):\d+", text)
+    if not m or not b or not t or m.group(1) != kernel_source_hash():
+        return None
+    here = (KERNEL_NAMES[plan["kernel"]], plan["tile_x"], plan["tile_y"], plan["tile_z"])
+    if (t.group(1), int(t.group(2)), int(t.group(3)), int(t.group(4))) != here:
         return None
     return float(b.group(1))
 
@@ -152,7 +157,7 @@ def main():
     achieved = algo_bytes / (ms_per_launch * 1e-3) / 1e9
     kname = {0: "k_collide", 1: "k_fused", 2: "k_fused_staged", 3: "k_fused_staged"}[kplan["kernel"]]
     log(f"[bench] {kname}: {ms_per_launch * 1e3:.1f} us per step, {achieved:.0f} GB/s algorithmic")
-    traffic = read_traffic(kname, args.workload, args.storage)
+    traffic = read_traffic(kname, args.workload, args.storage, kplan)
     del ksim
 
     result = {

@@ -284,9 +284,12 @@ int lb_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void 
 int lb_set_plan(lb_sim *s, const lb_plan *plan);
 int lb_get_plan(lb_sim *s, lb_plan *plan);
 
-/* Autotuner: time each candidate plan over `steps` steps (the steps are
- * taken: the state advances by steps * candidates), keep the fastest and
- * report it in *best (may be NULL).  Results are plan-independent. */
+/* Autotuner: time each candidate plan (split; fused, staged and rows tiles
+ * by z depth; each with and without graphs) over `steps` steps, time the
+ * three fastest once more, keep the one with the best time and report it
+ * in *best (may be NULL).  The timed steps are taken: the state advances by
+ * their number (lb_info's step).  Results are plan-independent, so tuning
+ * changes no result beyond that advance. */
 int lb_tune(lb_sim *s, int steps, lb_plan *best);
 
 int lb_info(lb_sim *s, lb_info_t *out);

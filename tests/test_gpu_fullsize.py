@@ -1,8 +1,9 @@
 """Parity at the full workload sizes, in the launch configurations bench.py
-times: 256^3 FP32 with the row-staged fused kernel (32 x 8 x 43 tiles, the
-default plan at this size) replayed from a HIP graph,
-512^3 with FP16 storage, and the 96-replica finite-size sweep in one handle.
-The oracle runs the whole lattice in FP64 on the host cores."""
+times: 256^3 FP32 with the row-staged fused kernel (64 x 4 x 86 tiles, the
+default plan and the tuner's usual pick at this size, and 32 x 8 x 43, the
+other near-tie) replayed from a HIP graph, 512^3 with FP16 storage, and the
+96-replica finite-size sweep in one handle.  The oracle runs the whole
+lattice in FP64 on the host cores."""
 import numpy as np
 import pytest
 
@@ -19,29 +20,34 @@ M0 = workloads.MODEL
 def test_256_fp32_bench_configuration():
     lbf = require_gpu()
     L, steps = 256, 10
-    say("256^3 fp32 rows 32x8x43, graph of 10 steps, sample every 10")
-    sim = lbf.Sim(L, workloads.SEED, sample_every=10, series_capacity=4, **M0)
-    sim.set_plan("rows", (32, 8, 43), 10)
-    sim.step(steps)
-    got = sim.fields(f=True)
-    mom = sim.moments(series=True)
     say("  oracle 256^3, 10 steps")
     orc = oracle.Sim(L, workloads.SEED, **M0)
     orc.step(steps)
     rho_o, j_o = orc.fields()
-    e = (rel_err(got["rho"], rho_o), rel_err(got["j"], j_o), rel_err(got["f"], orc.f))
-    say(f"  rel errors rho/j/f {e}")
-    assert max(e) <= 1e-5
     acc = moments.Accumulator(L)
     acc.add(rho_o, step=steps, j=j_o)
-    assert mom["n_samples"] == 1
-    for lv in mom["levels"]:
-        ref = acc.sums[lv["Lb"]]
-        for k in ("m2", "m4", "E", "E2", "abs_m"):
-            assert abs(lv[k] - ref[k]) <= 2e-5 * abs(ref[k]), (lv["Lb"], k)
-    # S(k) of a mode is a squared sum over planes; its FP32-trajectory error
-    # is set by the typical plane-sum size, so the bound scales with mean S
-    assert np.max(np.abs(mom["sk"] - acc.sk)) <= 2e-5 * np.mean(acc.sk)
+    for tile in ((64, 4, 86), (32, 8, 43)):
+        say(f"256^3 fp32 rows {tile}, graph of 10 steps, sample every 10")
+        sim = lbf.Sim(L, workloads.SEED, sample_every=10, series_capacity=4, **M0)
+        if tile == (64, 4, 86):
+            p = sim.plan()
+            assert (p["kernel"], p["tile_x"], p["tile_y"], p["tile_z"]) == (lbf.LB_KERNEL_ROWS, 64, 4, 86)
+        sim.set_plan("rows", tile, 10)
+        sim.step(steps)
+        got = sim.fields(f=True)
+        mom = sim.moments(series=True)
+        e = (rel_err(got["rho"], rho_o), rel_err(got["j"], j_o), rel_err(got["f"], orc.f))
+        say(f"  rel errors rho/j/f {e}")
+        assert max(e) <= 1e-5
+        assert mom["n_samples"] == 1
+        for lv in mom["levels"]:
+            ref = acc.sums[lv["Lb"]]
+            for k in ("m2", "m4", "E", "E2", "abs_m"):
+                assert abs(lv[k] - ref[k]) <= 2e-5 * abs(ref[k]), (lv["Lb"], k)
+        # S(k) of a mode is a squared sum over planes; its FP32-trajectory error
+        # is set by the typical plane-sum size, so the bound scales with mean S
+        assert np.max(np.abs(mom["sk"] - acc.sk)) <= 2e-5 * np.mean(acc.sk)
+        del sim
 
 
 def test_512_fp16_one_step():

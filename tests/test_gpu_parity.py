@@ -170,6 +170,26 @@ def test_fp16_plans_bit_identical(L):
         assert np.array_equal(s, states[0])
 
 
+def test_tuner_keeps_the_trajectory():
+    """lb_tune steps the state through every candidate plan (split, fused,
+    staged, rows; with and without graphs, sampling on): afterwards the
+    state equals that of a handle stepped as often with the default plan,
+    bit for bit, and the kept plan is one of the candidates."""
+    lbf = require_gpu()
+    L = 24
+    say("tuner L=24")
+    prm = dict(M0, sample_every=5)
+    a = lbf.Sim(L, 31, **prm)
+    best = a.tune(steps=4)
+    assert best["kernel"] in (lbf.LB_KERNEL_SPLIT, lbf.LB_KERNEL_FUSED, lbf.LB_KERNEL_STAGED, lbf.LB_KERNEL_ROWS)
+    assert a.plan() == best
+    a.step(3)
+    n = a.info()["step"]
+    b = lbf.Sim(L, 31, **prm)
+    b.step(n)
+    assert np.array_equal(a.fields(f=True)["f"], b.fields(f=True)["f"])
+
+
 def test_deterministic_repeat():
     lbf = require_gpu()
     say("repeat L=16")
