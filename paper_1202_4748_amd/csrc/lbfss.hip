@@ -144,6 +144,17 @@ void *dev_alloc(lb_sim *s, size_t bytes) {
     return p;
 }
 
+// Free one block of dev_alloc's (a temporary) before the handle goes.
+void dev_release(lb_sim *s, void *p, size_t bytes) {
+    if (!p) return;
+    if (bytes == 0) bytes = 256;
+    auto it = std::find(s->blocks.begin(), s->blocks.end(), p);
+    if (it != s->blocks.end()) s->blocks.erase(it);
+    if (s->alloc.free_) s->alloc.free_(p, s->alloc.ctx);
+    else (void)hipFree(p);
+    s->device_bytes -= (int64_t)bytes;
+}
+
 void dev_free_all(lb_sim *s) {
     for (void *p : s->blocks) {
         if (s->alloc.free_) s->alloc.free_(p, s->alloc.ctx);
@@ -855,8 +866,9 @@ int lb_moments(lb_sim *s, int replica, lb_moments_t *out, double *sk, double *se
     if (sk) std::memcpy(sk, acc.data() + (size_t)kMoments * d.nlev, sizeof(double) * 3 * d.n_k);
     if (series && out->series_len > 0) {
         std::vector<double> ring((size_t)d.series_cap * d.rec_len);
-        HIPCHK(hipMemcpy(ring.data(), s->d_series + d.series_off, sizeof(double) * ring.size(),
-                         hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(ring.data(), s->d_series + d.series_off, sizeof(double) * ring.size(),
+                              hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
         const int64_t first = ns > d.series_cap ? ns % d.series_cap : 0;
         for (int64_t i = 0; i < out->series_len; ++i) {
             const int64_t slot = (first + i) % d.series_cap;
@@ -1068,15 +1080,9 @@ int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f) {
     if (rc == LB_OK && f && hipMemcpyAsync(f, df, sizeof(double) * Q * N, hipMemcpyDeviceToHost, s->stream))
         rc = LB_EDEVICE;
     if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
-    // release the temporaries (they are the most recent blocks)
-    for (void *p : {(void *)df, (void *)dj, (void *)drho}) {
-        if (!p) continue;
-        auto it = std::find(s->blocks.begin(), s->blocks.end(), p);
-        if (it != s->blocks.end()) s->blocks.erase(it);
-        if (s->alloc.free_) s->alloc.free_(p, s->alloc.ctx);
-        else (void)hipFree(p);
-    }
-    s->device_bytes -= (int64_t)((rho ? N : 0) + (j ? 3 * N : 0) + (f ? Q * N : 0)) * (int64_t)sizeof(double);
+    dev_release(s, df, sizeof(double) * Q * N);
+    dev_release(s, dj, sizeof(double) * 3 * N);
+    dev_release(s, drho, sizeof(double) * N);
     if (rc) return rc;
     return check_err(s);
 }
@@ -1102,11 +1108,7 @@ int lb_set_populations(lb_sim *s, int replica, const double *f) {
         if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
     }
     if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
-    auto it = std::find(s->blocks.begin(), s->blocks.end(), (void *)df);
-    if (it != s->blocks.end()) s->blocks.erase(it);
-    if (s->alloc.free_) s->alloc.free_(df, s->alloc.ctx);
-    else (void)hipFree(df);
-    s->device_bytes -= (int64_t)bytes;
+    dev_release(s, df, bytes);
     if (rc) return rc;
     return check_err(s);
 }
