@@ -55,7 +55,8 @@ def read_traffic(kname, workload, storage, plan):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary, or None if absent, taken on other kernel sources or on
     another kernel or tile (plan: the plan dict being timed)."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kname}_{workload}_{storage}.md")
+    name = workload if workload.endswith("_" + storage) else f"{workload}_{storage}"
+    path = os.path.join(ROOT, "profiles", f"traffic_{kname}_{name}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
