@@ -241,14 +241,21 @@ def batched_vs_plain(lbf, workloads, torch, steps=200):
     return out
 
 
-def cpu_baseline(L, wl):
-    """The FP64 oracle timed on the host cores on one step of the same lattice."""
+def cpu_baseline(L, wl, min_seconds=10.0, max_steps=20):
+    """The FP64 oracle timed on the host cores on whole steps of the same
+    lattice: steps are taken until at least ``min_seconds`` have passed
+    (at most ``max_steps``)."""
     import oracle
     threads = oracle.default_threads()
-    log(f"[bench] cpu baseline: oracle {L}^3, 1 step, {threads} threads")
+    log(f"[bench] cpu baseline: oracle {L}^3, {threads} threads, >= {min_seconds:.0f} s of steps")
     orc = oracle.Sim(L, 20120221, nthreads=threads, **wl)
+    steps = 0
     t0 = time.perf_counter()
-    orc.step(1)
+    while steps < max_steps:
+        orc.step(1)
+        steps += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
     dt = time.perf_counter() - t0
     model = ""
     try:
@@ -258,8 +265,8 @@ def cpu_baseline(L, wl):
                 break
     except OSError:
         pass
-    return {"value": round(L ** 3 / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"one FP64 step of the {L}^3 lattice ({L ** 3} site updates, {dt:.1f} s)",
+    return {"value": round(steps * L ** 3 / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the {L}^3 lattice ({steps * L ** 3} site updates, {dt:.1f} s)",
             "cpu": model}
 
 
