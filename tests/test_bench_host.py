@@ -1,0 +1,39 @@
+"""Host-side behaviour of bench.py (no GPU): the one-GPU rule and the
+traffic lookup that ties counter summaries to the kernel sources and plan."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_traffic_only_for_the_profiled_sources_and_plan(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    h = bench.kernel_source_hash()
+    (prof / "traffic_k_fused_staged_d3q19_256_fp32.md").write_text(
+        "# HBM traffic: k_fused_staged, d3q19_256, fp32 storage, plan rows:64:4:86:10\n"
+        f"traffic_bytes_per_launch: 2.5e+09\nsource_hash: {h}\n")
+    (prof / "traffic_k_fused_staged_d3q19_512_fp16.md").write_text(
+        "# HBM traffic: k_fused_staged, d3q19_512_fp16, fp16 storage, plan rows:64:4:86:10\n"
+        "traffic_bytes_per_launch: 1e+10\nsource_hash: 0000000000000000\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    rows = {"kernel": 3, "tile_x": 64, "tile_y": 4, "tile_z": 86, "graph_steps": 20}
+    assert bench.read_traffic("k_fused_staged", "d3q19_256", "fp32", rows) == 2.5e9
+    # another tile, another kernel or other sources: no traffic
+    assert bench.read_traffic("k_fused_staged", "d3q19_256", "fp32", dict(rows, tile_z=43)) is None
+    assert bench.read_traffic("k_fused_staged", "d3q19_256", "fp32", dict(rows, kernel=2)) is None
+    assert bench.read_traffic("k_fused_staged", "d3q19_512_fp16", "fp16", rows) is None
+    assert bench.read_traffic("k_fused", "d3q19_256", "fp32", rows) is None
