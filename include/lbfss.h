@@ -152,7 +152,8 @@ enum {
 typedef struct {
     int32_t kernel;      /* LB_KERNEL_SPLIT, _FUSED, _STAGED or _ROWS */
     int32_t tile_x;      /* fused: tile edge along x; (tile_x, tile_y) in {(32,8), (16,16),
-                          * (16,8), (64,4)}, (64,4) not staged; clamped to L */
+                          * (16,8), (64,4), (64,8)}, (64,4) not staged, (64,8) rows only;
+                          * clamped to L */
     int32_t tile_y;      /* fused: tile edge along y */
     int32_t tile_z;      /* fused: planes marched by one workgroup */
     int32_t graph_steps; /* > 0: capture this many steps (rounded up to even) in a
@@ -165,10 +166,10 @@ typedef struct lb_sim lb_sim; /* opaque, owned by the library */
 /* One periodic L^3 lattice (L >= 4).  Initial state: rho = rho_c +
  * init_sigma g with g the first Box-Muller normal of Philox call
  * (site, 0, 1 << 16, 0), u = 0, f_i = w_i rho.  *out receives the handle.
- * Initial plan: LB_KERNEL_ROWS where every L allows it (else FUSED), on
- * 64 x 4 tiles in three (FP32) or six (FP16) z slabs when the largest L is
- * at least 128, on 32 x 8 tiles otherwise; direct launches (lb_set_plan and
- * lb_tune change it; results do not depend on it).
+ * Initial plan: LB_KERNEL_ROWS where every L allows it (else FUSED); when
+ * the largest L is at least 128, on 64 x 4 tiles in three z slabs (FP32) or
+ * 64 x 8 tiles in six (FP16), else on 32 x 8 tiles; direct launches
+ * (lb_set_plan and lb_tune change it; results do not depend on it).
  * Errors: LB_EINVAL for L < 4, L > 1024, tau <= 1/2, kT < 0, kappa < 0,
  * b < 0, rho_c <= 0, init_sigma < 0, bad storage, flags, sample_every < 0,
  * n_levels < 0 or series_capacity < 0; LB_ENOMEM; LB_EDEVICE. */

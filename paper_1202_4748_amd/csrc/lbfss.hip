@@ -744,15 +744,15 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
     default_fused_tile(s->hdesc, def.tile_x, def.tile_y, def.tile_z);
     if (rows_ok(s)) {
         def.kernel = LB_KERNEL_ROWS;
-        // large lattices: 64 x 4 tiles (wider source rows); FP32 in three z
-        // slabs (L = 256: 768 tiles, one round of three workgroups per CU),
-        // FP16 in six (four workgroups per CU); 32 x 8 measured 2% (FP32)
-        // and 10% (FP16) slower
+        // large lattices, wider source rows: FP32 on 64 x 4 tiles in three z
+        // slabs (L = 256: 768 tiles, one round of three workgroups per CU;
+        // 32 x 8 measured 2% slower), FP16 on 64 x 8 tiles in six (two
+        // 512-thread workgroups per CU; 64 x 4 measured 5%, 32 x 8 15% slower)
         int maxL = 0;
         for (const auto &d : s->hdesc) maxL = std::max(maxL, d.L);
         if (maxL >= 128) {
             def.tile_x = 64;
-            def.tile_y = 4;
+            def.tile_y = s->storage == LB_FP16 ? 8 : 4;
             def.tile_z = s->storage == LB_FP16 ? (maxL + 5) / 6 : (maxL + 2) / 3;
         }
     }

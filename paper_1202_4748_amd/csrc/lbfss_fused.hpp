@@ -624,6 +624,7 @@ inline std::vector<std::array<int, 3>> fused_tile_candidates(const std::vector<R
     for (int tz : tzs)
         if (tz <= std::max(maxL, 16)) {
             c.push_back({64, 4, tz});
+            c.push_back({64, 8, tz});
             c.push_back({32, 8, tz});
             c.push_back({16, 16, tz});
         }
@@ -665,7 +666,11 @@ inline bool staged_tile_ok(int tx, int ty) {
 }
 
 // the rows staging also takes 64 x 4 tiles (two halo sites for some threads)
-inline bool rows_tile_ok(int tx, int ty) { return staged_tile_ok(tx, ty) || (tx == 64 && ty == 4); }
+// and 64 x 8 tiles (512 threads: fewer halo rows per site; two workgroups
+// per CU with FP16 storage, one with FP32)
+inline bool rows_tile_ok(int tx, int ty) {
+    return staged_tile_ok(tx, ty) || (tx == 64 && ty == 4) || (tx == 64 && ty == 8);
+}
 
 
 template <typename T, bool ROWS, bool SNAP>
@@ -680,6 +685,9 @@ void launch_staged_snap(const RepDesc *desc, const FusedTile *tiles, int n_tiles
                            in, out, step, koff, err, snap, total);
     else if (ROWS && tx == 64 && ty == 4)
         hipLaunchKernelGGL((k_fused_staged<T, 64, 4, true, SNAP>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles,
+                           in, out, step, koff, err, snap, total);
+    else if (ROWS && tx == 64 && ty == 8)
+        hipLaunchKernelGGL((k_fused_staged<T, 64, 8, true, SNAP>), dim3(n_tiles), dim3(512), 0, stream, desc, tiles,
                            in, out, step, koff, err, snap, total);
     else
         hipLaunchKernelGGL((k_fused_staged<T, 32, 8, ROWS, SNAP>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles,

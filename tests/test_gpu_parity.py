@@ -67,7 +67,8 @@ def test_config0_100_steps(kernel):
                                            (12, "rows", (16, 16, 5)), (12, "staged", (16, 8, 5)),
                                            (20, "rows", (16, 16, 16)), (37, "staged", (32, 8, 16)),
                                            (40, "rows", (32, 8, 7)), (44, "rows", (16, 8, 9)),
-                                           (36, "fused", (64, 4, 5)), (36, "rows", (64, 4, 5))])
+                                           (36, "fused", (64, 4, 5)), (36, "rows", (64, 4, 5)),
+                                           (40, "rows", (64, 8, 6))])
 def test_ragged_sizes(L, kernel, tile):
     """Sizes not divisible by the tile (partial tiles, wrap-around halos, the
     source rows of the rows staging wrapping more than once on L = 4)."""
@@ -142,7 +143,7 @@ def test_plans_bit_identical():
                             ("fused", (32, 8, 5), 6), ("split", (0, 0, 0), 4), ("fused", (64, 4, 7), 0),
                             ("staged", (32, 8, 9), 0), ("staged", (16, 16, 24), 0), ("staged", (16, 8, 5), 4),
                             ("rows", (32, 8, 9), 0), ("rows", (16, 16, 24), 6), ("rows", (16, 8, 5), 0),
-                            ("rows", (64, 4, 7), 0)]:
+                            ("rows", (64, 4, 7), 0), ("rows", (64, 8, 7), 0), ("rows", (64, 8, 5), 4)]:
         sim = lbf.Sim(L, 11, **M0)
         sim.set_plan(kernel, tile, g)
         sim.step(13)
@@ -154,14 +155,15 @@ def test_plans_bit_identical():
 @pytest.mark.parametrize("L", [8, 24, 40])
 def test_fp16_plans_bit_identical(L):
     """FP16 storage: split, the register-ring fused kernel and the rows
-    staging (8-half chunks) give the same bits, with partial tiles (L = 40
-    against 32- and 64-wide tiles) and the source rows wrapping on L = 8."""
+    staging (8-half chunks; 64 x 8 tiles with 512 threads too) give the same
+    bits, with partial tiles (L = 40 against 32- and 64-wide tiles) and the
+    source rows wrapping on L = 8."""
     lbf = require_gpu()
     say(f"fp16 plans L={L}")
     states = []
     for kernel, tile, g in [("split", (0, 0, 0), 0), ("fused", (32, 8, 7), 0), ("fused", (64, 4, 5), 3),
                             ("rows", (32, 8, 7), 0), ("rows", (64, 4, 9), 0), ("rows", (16, 16, 5), 4),
-                            ("rows", (16, 8, 3), 0)]:
+                            ("rows", (16, 8, 3), 0), ("rows", (64, 8, 5), 0), ("rows", (64, 8, 7), 3)]:
         sim = lbf.Sim(L, 21, storage="fp16", **M0)
         sim.set_plan(kernel, tile, g)
         sim.step(9)
