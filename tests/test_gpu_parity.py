@@ -280,3 +280,44 @@ def test_separate_relaxation_times(kernel):
         sim.step(1)
         orc.step(1)
         _compare(sim, orc, TOL32, f"step {t + 1}")
+
+
+@pytest.mark.parametrize("kernel", ["split", "fused", "rows"])
+def test_rest_state_is_exact_without_noise(kernel):
+    """kT = 0 and a uniform density: every population is w_i rho_c at rest;
+    the force, the noise and every moment beyond rho are zero, so the state
+    stays exactly the rest state (stored deviations exactly zero)."""
+    lbf = require_gpu()
+    sim = lbf.Sim(12, 5, **dict(M0, kT=0.0, init_sigma=0.0))
+    sim.set_plan(kernel, (16, 16, 5))
+    sim.step(12)
+    g = sim.fields(f=True)
+    # every site identical (the stored deviations are exactly zero); the
+    # exported rho sums w_i rho_c in FP64, equal to rho_c up to rounding
+    assert np.array_equal(g["f"], np.broadcast_to(g["f"][:, :1], g["f"].shape))
+    assert np.all(g["rho"] == g["rho"][0]) and abs(g["rho"][0] - M0["rho_c"]) < 1e-15
+    assert not np.any(g["j"])
+
+
+@pytest.mark.parametrize("name,prm", [
+    ("no noise", dict(kT=0.0)),
+    ("tau near 1/2", dict(tau=0.51)),
+    ("no thermodynamic terms", dict(a=0.0, b=0.0, kappa=0.0)),
+    ("strong noise", dict(kT=1e-3, tau=0.6)),
+])
+def test_degenerate_parameters(name, prm):
+    """Edges of the parameter range against the oracle, every step of 10:
+    deterministic dynamics (kT = 0), relaxation factor near -1 (tau = 0.51),
+    the force reduced to the cancellation of the lattice pressure
+    (a = b = kappa = 0), and ten times the workload's noise."""
+    lbf = require_gpu()
+    L = 12
+    p = dict(M0, **prm)
+    say(f"degenerate: {name}")
+    sim = lbf.Sim(L, 23, **p)
+    sim.set_plan("rows", (16, 16, 5))
+    orc = oracle.Sim(L, 23, **p)
+    for t in range(10):
+        sim.step(1)
+        orc.step(1)
+        _compare(sim, orc, TOL32, f"{name} step {t + 1}")
