@@ -265,9 +265,20 @@ def cpu_baseline(L, wl, min_seconds=10.0, max_steps=20):
                 break
     except OSError:
         pass
-    return {"value": round(steps * L ** 3 / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} FP64 steps of the {L}^3 lattice ({steps * L ** 3} site updates, {dt:.1f} s)",
-            "cpu": model}
+    out = {"value": round(steps * L ** 3 / dt / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} FP64 steps of the {L}^3 lattice ({steps * L ** 3} site updates, {dt:.1f} s)",
+           "cpu": model}
+    if threads > 1:
+        # the same oracle on one thread, one step
+        del orc
+        one = oracle.Sim(L, 20120221, nthreads=1, **wl)
+        log(f"[bench] cpu baseline: oracle {L}^3, 1 thread, 1 step")
+        t0 = time.perf_counter()
+        one.step(1)
+        dt1 = time.perf_counter() - t0
+        out["one_core"] = {"value": round(L ** 3 / dt1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                           "sample": f"1 FP64 step of the {L}^3 lattice ({dt1:.1f} s)"}
+    return out
 
 
 if __name__ == "__main__":
