@@ -40,14 +40,22 @@ def log(*a):
 STEP_KERNEL_SOURCES = ("lbfss_device.hpp", "lbfss_step.hpp", "lbfss_fused.hpp")
 
 
-def kernel_source_hash():
-    """Hash of the sources the step kernels are built from (the traffic
+def code_of(text):
+    """C++ source without comments and whitespace: what the kernels are built
+    from, so that a comment edit does not invalidate counter summaries."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "".join(text.split())
+
+
+def kernel_source_hash(csrc=None):
+    """Hash of the code the step kernels are built from (the traffic
     counters are only valid for the kernel they were taken on)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1202_4748_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_1202_4748_amd", "csrc")
     for name in STEP_KERNEL_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, name)) as fh:
+            h.update(code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,7 +1,8 @@
 // Fused step: one pass per time step.
 //
-// A 256-thread workgroup owns an x-y tile of TX x TY = 256 sites of one
-// replica and marches through a range of z planes, one thread per tile site.
+// A workgroup owns an x-y tile of TX x TY sites of one replica (256
+// threads; 128 for 16 x 8 tiles, 512 for 64 x 8) and marches through a
+// range of z planes, one thread per tile site.
 // For each plane p it
 //   (a) pulls the 19 populations of its site into a register ring (three
 //       planes deep) and puts the site density in an LDS ring; threads also
@@ -9,7 +10,8 @@
 //   (b) derives the chemical potential of plane p - 1 on the tile and a
 //       one-site halo (LDS ring);
 //   (c) collides plane p - 2 from the register ring: force from the LDS
-//       stencils, moment-space collision with Philox noise, store.
+//       stencils, moment-space collision with Philox noise, non-temporal
+//       store.
 // Populations are read from memory once per site; the halo pulls are
 // interior pulls of a neighbouring tile, which the XCD-aware workgroup order
 // schedules on the same XCD at the same time, so they are served by its L2.
@@ -306,15 +308,17 @@ __device__ __forceinline__ uint32_t pull_off(int q, const PlaneOffs &o) {
 }
 
 //
-// ROWS selects how plane p + 1 is staged.  false: every thread loads the 19
-// pulled values of its tile site, and threads of the first waves those of one
-// halo site each (dword per lane, the slot of a value is its site).  true:
-// for each population the workgroup copies the unshifted source rectangle
-// that the pulls of the tile and its two-site halo read, TY + 4 rows of
-// TX + 8 columns starting at x0 - 4 (16-byte aligned when L is a multiple
-// of 4), with 16-byte loads spread over all waves; a pulled value is then the
-// rectangle entry at the site's row and at column ex + 2 - cx_q.  The rows
-// mode issues about a quarter of the load instructions for the same data.
+// ROWS selects how plane p + 1 is staged.  false (FP32 only): every thread
+// loads the 19 pulled values of its tile site, and threads of the first
+// waves those of one halo site each (dword per lane, the slot of a value is
+// its site).  true: for each population the workgroup copies the unshifted
+// source rectangle that the pulls of the tile and its two-site halo read,
+// TY + 4 rows of TX + 2 CH columns starting at x0 - CH, with CH = 4 floats
+// or 8 halves per 16-byte load (aligned when L is a multiple of CH); the
+// loads are spread over all waves, and a pulled value is then the
+// rectangle entry at the site's row and at column ex + CH - 2 - cx_q.  The
+// rows mode issues about a quarter of the load instructions for the same
+// data.  Tiles of 512 threads (64 x 8) have eight waves; the rest four.
 template <typename T, int TX, int TY, bool ROWS, bool SNAP>
 __global__ void __launch_bounds__(TX * TY)
 k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const T *__restrict__ pop,

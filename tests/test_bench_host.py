@@ -37,3 +37,11 @@ def test_traffic_only_for_the_profiled_sources_and_plan(tmp_path, monkeypatch):
     assert bench.read_traffic("k_fused_staged", "d3q19_256", "fp32", dict(rows, kernel=2)) is None
     assert bench.read_traffic("k_fused_staged", "d3q19_512_fp16", "fp16", rows) is None
     assert bench.read_traffic("k_fused", "d3q19_256", "fp32", rows) is None
+
+
+def test_source_hash_ignores_comments_only():
+    a = "int f(int x) { // twice\n  return 2 * x; /* doubled */ }\n"
+    b = "int f(int x) {\n    // the double of x\n    return 2 * x;\n}\n"
+    c = "int f(int x) { return 3 * x; }\n"
+    assert bench.code_of(a) == bench.code_of(b)
+    assert bench.code_of(a) != bench.code_of(c)
