@@ -280,9 +280,11 @@ int lb_reset_moments(lb_sim *s);
  * NULL selects the handle's own stream).  Synchronises the previous stream. */
 int lb_set_stream(lb_sim *s, void *hip_stream);
 
-/* Device allocator used by handles created afterwards (process-wide).
- * alloc(bytes, ctx) returns device memory or NULL; free_(ptr, ctx) releases
- * it.  NULL functions restore hipMalloc / hipFree. */
+/* Device allocator used by handles created afterwards (process-wide; each
+ * handle keeps the one it was created with until lb_destroy).  alloc(bytes,
+ * ctx) returns device memory or NULL; free_(ptr, ctx) releases it.  Both
+ * NULL restore hipMalloc / hipFree; exactly one NULL is LB_EINVAL.  Not
+ * synchronised: call it while no other thread creates handles. */
 int lb_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void *), void *ctx);
 
 /* Launch plan; LB_EINVAL for unknown kernels or tiles. */
