@@ -72,7 +72,24 @@ enum {
 enum { LB_FP32 = 0, LB_FP16 = 1 };
 
 /* lb_params.flags */
-enum { LB_FORCE_OFF = 1 /* F = 0: the ideal lattice gas (a test of the noise) */ };
+enum {
+    LB_FORCE_OFF = 1,   /* F = 0: the ideal lattice gas (a test of the noise) */
+    LB_EQ_PRESSURE = 2  /* the paper's own model (Sec. III A) on D3Q19: no force; the
+                         * non-ideal pressure tensor of Eq. (press-th) carried by the
+                         * equilibrium, whose second moment is Eq. (holdych-cond) (the
+                         * scalar pressure on the moving populations, the rest one takes
+                         * the remainder of rho), BGK with one tau (tau_bulk = tau_ghost =
+                         * 0), and noise with the local-sound-speed covariance that keeps
+                         * the stationary population covariance independent of the wave
+                         * vector (on D2Q9 it is Eq. (lbnoise)): on the bulk moment and the
+                         * fourth-order ghost, M_44 = 5/3 - 3 c_s^2, M_4,16 = 3 c_s^2 - 1,
+                         * M_16,16 = 3 - 3 c_s^2 in units of 3 rho kT (1/tau)(2 - 1/tau),
+                         * c_s^2 = rho (a + 3 b (rho - rho_c)^2); c_s^2 >= 1/2 with kT > 0
+                         * raises LB_EUNSTABLE.  Mass and momentum are conserved exactly.
+                         * Split plan only; FP32 storage only (at rest this model keeps
+                         * nearly all mass on the rest population, so the stored
+                         * deviations are O(1)); not with LB_FORCE_OFF; equal in a batch. */
+};
 
 #define LB_MAX_LEVELS 16
 
@@ -87,7 +104,7 @@ typedef struct {
     int32_t storage;   /* LB_FP32 or LB_FP16 */
     int32_t sample_every; /* > 0: sample after every such step; 0: never */
     int32_t n_levels;  /* block edges L_b = L / 2^l, l = 1..n_levels while integer; 0 = all */
-    int32_t flags;     /* LB_FORCE_OFF or 0 */
+    int32_t flags;     /* LB_FORCE_OFF, LB_EQ_PRESSURE or 0 */
     int32_t series_capacity; /* per-sample records kept (ring buffer); 0 = none */
     int32_t hist_bins; /* > 0: histogram every level's box values m over this many equal
                         * bins of [-hist_range, hist_range) (<= LB_MAX_HIST_BINS); 0 = none */

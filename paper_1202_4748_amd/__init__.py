@@ -19,6 +19,7 @@ Q = 19
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
 LB_FP32, LB_FP16 = 0, 1
 LB_FORCE_OFF = 1
+LB_EQ_PRESSURE = 2
 LB_KERNEL_SPLIT, LB_KERNEL_FUSED, LB_KERNEL_STAGED, LB_KERNEL_ROWS = 0, 1, 2, 3
 LB_MAX_LEVELS = 16
 
@@ -196,10 +197,11 @@ def _use_torch():
 
 def make_params(a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, init_sigma=1e-3,
                 storage="fp32", sample_every=0, n_levels=0, force_off=False, series_capacity=0,
-                hist_bins=0, hist_range=0.0, sk3_stride=0, tau_bulk=0.0, tau_ghost=0.0):
+                hist_bins=0, hist_range=0.0, sk3_stride=0, tau_bulk=0.0, tau_ghost=0.0, eq_pressure=False):
     st = {"fp32": LB_FP32, "fp16": LB_FP16, LB_FP32: LB_FP32, LB_FP16: LB_FP16}[storage]
     return Params(a, b, kappa, rho_c, kT, tau, init_sigma, st, sample_every, n_levels,
-                  LB_FORCE_OFF if force_off else 0, series_capacity, int(hist_bins), float(hist_range),
+                  (LB_FORCE_OFF if force_off else 0) | (LB_EQ_PRESSURE if eq_pressure else 0),
+                  series_capacity, int(hist_bins), float(hist_range),
                   int(sk3_stride), 0, float(tau_bulk), float(tau_ghost))
 
 

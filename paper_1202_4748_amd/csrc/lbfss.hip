@@ -16,6 +16,7 @@
 #include "lbfss_sample.hpp"
 #include "lbfss_sk3.hpp"
 #include "lbfss_d2q9.hpp"
+#include "lbfss_meq.hpp"
 
 using namespace lbfss;
 
@@ -42,6 +43,7 @@ struct lb_sim {
     int64_t device_bytes = 0;
 
     int storage = LB_FP32;
+    bool eq_pressure = false;  // LB_EQ_PRESSURE: the paper's model (split kernels)
     int nrep = 0;
     std::vector<int> L;
     std::vector<lb_params> P;
@@ -193,7 +195,13 @@ int check_params(int L, const lb_params *p) {
         !(p->init_sigma >= 0) || !std::isfinite(p->a))
         return LB_EINVAL;
     if (p->storage != LB_FP32 && p->storage != LB_FP16) return LB_EINVAL;
-    if ((p->flags & ~LB_FORCE_OFF) != 0) return LB_EINVAL;
+    if ((p->flags & ~(LB_FORCE_OFF | LB_EQ_PRESSURE)) != 0) return LB_EINVAL;
+    // the paper's model: no force, one tau, and FP32 storage (its fluid at rest
+    // keeps nearly all mass on the rest population, so the stored deviations
+    // from w_i rho_c are O(1) and binary16 would keep ~1e-3 of them)
+    if ((p->flags & LB_EQ_PRESSURE) && ((p->flags & LB_FORCE_OFF) || p->tau_bulk != 0 || p->tau_ghost != 0 ||
+                                        p->storage != LB_FP32))
+        return LB_EINVAL;
     if (p->sample_every < 0 || p->n_levels < 0 || p->series_capacity < 0) return LB_EINVAL;
     if (p->hist_bins < 0 || p->hist_bins > LB_MAX_HIST_BINS) return LB_EINVAL;
     if (p->hist_bins > 0 && !(p->hist_range > 0 && std::isfinite(p->hist_range))) return LB_EINVAL;
@@ -207,6 +215,20 @@ void launch_step(lb_sim *s, int cur, int koff, float *snap) {
     const T *in = (const T *)s->pop[cur];
     T *out = (T *)s->pop[cur ^ 1];
     const int64_t total = s->total_sites;
+    if (s->eq_pressure) {
+        const int64_t nb = ceil_div(s->total_sites, kBlock);
+        hipLaunchKernelGGL(k_density<T>, dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc, s->nrep,
+                           s->total_sites, in, s->d_drho);
+        if (snap)
+            hipLaunchKernelGGL((k_meq_collide<T, true>), dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc,
+                               s->nrep, s->total_sites, in, out, (const float *)s->d_drho,
+                               (const uint64_t *)s->d_step, koff, s->d_err, snap);
+        else
+            hipLaunchKernelGGL((k_meq_collide<T, false>), dim3((unsigned)nb), dim3(kBlock), 0, s->stream, s->d_desc,
+                               s->nrep, s->total_sites, in, out, (const float *)s->d_drho,
+                               (const uint64_t *)s->d_step, koff, s->d_err, snap);
+        return;
+    }
     if (s->plan.kernel == LB_KERNEL_ROWS && s->n_tiles > 0) {
         launch_fused_staged<T, true>(s->d_desc, s->d_tiles, s->n_tiles, in, out, s->d_step, koff, s->d_err,
                                      s->plan.tile_x, s->plan.tile_y, s->stream, snap, total);
@@ -661,12 +683,14 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
         int rc = check_params(L[r], &p[r]);
         if (rc) return rc;
         if (p[r].storage != p[0].storage || p[r].sample_every != p[0].sample_every ||
-            p[r].sk3_stride != p[0].sk3_stride)
+            p[r].sk3_stride != p[0].sk3_stride ||
+            (p[r].flags & LB_EQ_PRESSURE) != (p[0].flags & LB_EQ_PRESSURE))
             return LB_EINVAL;
     }
     lb_sim *s = new (std::nothrow) lb_sim();
     if (!s) return LB_ENOMEM;
     s->alloc = g_alloc;
+    s->eq_pressure = (p[0].flags & LB_EQ_PRESSURE) != 0;
     int rc = LB_OK;
     auto fail = [&](int code) {
         lb_destroy(s);
@@ -1150,6 +1174,7 @@ int lb_set_plan(lb_sim *s, const lb_plan *plan) {
         const int64_t P = graph_period(s);
         p.graph_steps = (int)(ceil_div(p.graph_steps, P) * P);
     }
+    if (s->eq_pressure && p.kernel != LB_KERNEL_SPLIT) return LB_EINVAL;  // the paper's model: split only
     if (p.kernel == LB_KERNEL_FUSED || p.kernel == LB_KERNEL_STAGED || p.kernel == LB_KERNEL_ROWS) {
         if (p.kernel == LB_KERNEL_FUSED && !fused_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
         if (p.kernel == LB_KERNEL_STAGED && !staged_tile_ok(p.tile_x, p.tile_y)) return LB_EINVAL;
