@@ -50,7 +50,12 @@ def test_invalid_arguments_rejected_before_device(L):
                   (16, lbf.make_params(hist_bins=-1)), (16, lbf.make_params(hist_bins=4097, hist_range=1.0)),
                   (16, lbf.make_params(hist_bins=10, hist_range=0.0)),
                   (16, lbf.make_params(hist_bins=10, hist_range=float("inf"))),
-                  (16, lbf.make_params(sample_every=5, sk3_stride=-1))]:
+                  (16, lbf.make_params(sample_every=5, sk3_stride=-1)),
+                  # the paper's model: FP32 storage, one tau, no force switch
+                  (16, lbf.make_params(eq_pressure=True, storage="fp16")),
+                  (16, lbf.make_params(eq_pressure=True, force_off=True)),
+                  (16, lbf.make_params(eq_pressure=True, tau_bulk=1.2)),
+                  (16, lbf.make_params(eq_pressure=True, tau_ghost=0.9))]:
         assert L.lb_create(L_, ctypes.byref(p), 1, ctypes.byref(h)) == lbf.LB_EINVAL
     bad = lbf.make_params()
     bad.storage = 7
@@ -74,6 +79,12 @@ def test_invalid_arguments_rejected_before_device(L):
         assert L.lb2_create(L_, ctypes.byref(p2), 1, ctypes.byref(h2)) == lbf.LB_EINVAL
     assert L.lb2_step(None, 1) == lbf.LB_EINVAL
     assert L.lb2_spectra(None, None, None, None, None, None, None) == lbf.LB_EINVAL
+    bad_flag = lbf.make_params()
+    bad_flag.flags = 4
+    assert L.lb_create(16, ctypes.byref(bad_flag), 1, ctypes.byref(h)) == lbf.LB_EINVAL
+    # the model must agree across a batch
+    P3 = (lbf.Params * 2)(lbf.make_params(eq_pressure=True), lbf.make_params())
+    assert L.lb_create_batch(2, Ls, P3, S, ctypes.byref(h)) == lbf.LB_EINVAL
     # sk3_stride must agree across a batch
     Ls2 = (ctypes.c_int * 2)(8, 8)
     P2 = (lbf.Params * 2)(lbf.make_params(sample_every=2, sk3_stride=1), lbf.make_params(sample_every=2))
