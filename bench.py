@@ -11,7 +11,8 @@ device memory before the timed region.
 Also reported on the same line:
   roofline      the fused step kernel against the 8 TB/s HBM peak, with
                 152 algorithmic bytes per site update (19 FP32 populations
-                read + 19 written), timed with HIP events on its stream;
+                read + 19 written), timed with HIP events on its stream, and
+                against a 1 GiB device-to-device copy timed on the same GPU;
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload;
   batched       the 96-replica finite-size sweep in one handle against the
                 same 96 replicas run one after another (same seeds and steps,
@@ -168,6 +169,8 @@ def main():
     log(f"[bench] {kname}: {ms_per_launch * 1e3:.1f} us per step, {achieved:.0f} GB/s algorithmic")
     traffic = read_traffic(kname, args.workload, args.storage, kplan)
     del ksim
+    copy_gbs = device_copy_gbs(torch, stream)
+    log(f"[bench] device copy: {copy_gbs:.0f} GB/s (read + write of 1 GiB)")
 
     result = {
         "metric": "MLUPS D3Q19 fluctuating step, % HBM roofline; batched vs plain at equal accuracy",
@@ -189,7 +192,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_site": BYTES_PER_SITE[args.storage],
-                     "us_per_launch": round(ms_per_launch * 1e3, 2)},
+                     "us_per_launch": round(ms_per_launch * 1e3, 2),
+                     "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "mass": mom["mass"],
     }
 
@@ -200,6 +204,24 @@ def main():
         result["cpu_baseline"] = cpu_baseline(L, wl)
 
     print(json.dumps(result), flush=True)
+
+
+def device_copy_gbs(torch, stream, nbytes=1 << 30, reps=5):
+    """Bandwidth of a plain device-to-device copy on this GPU (bytes read plus
+    bytes written per second), the practical ceiling a streaming kernel is
+    compared with beside the nominal peak."""
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def batched_vs_plain(lbf, workloads, torch, steps=200):
