@@ -17,6 +17,11 @@ Also reported on the same line:
   batched       the 96-replica finite-size sweep in one handle against the
                 same 96 replicas run one after another (same seeds and steps,
                 so the results are identical).
+
+--workload d3q19_256_eq | d2q9_256 | d2q9_2048 times the paper's own model
+(the GL pressure in the equilibrium) instead, on D3Q19 or on D2Q9, with its
+own JSON line: the roofline over its density and collide passes and the
+NumPy oracle of that model on one host thread.
 """
 import argparse
 import hashlib
@@ -49,12 +54,12 @@ def code_of(text):
     return "".join(text.split())
 
 
-def kernel_source_hash(csrc=None):
+def kernel_source_hash(csrc=None, names=STEP_KERNEL_SOURCES):
     """Hash of the code the step kernels are built from (the traffic
     counters are only valid for the kernel they were taken on)."""
     h = hashlib.sha256()
     csrc = csrc or os.path.join(ROOT, "paper_1202_4748_amd", "csrc")
-    for name in STEP_KERNEL_SOURCES:
+    for name in names:
         with open(os.path.join(csrc, name)) as fh:
             h.update(code_of(fh.read()).encode())
     return h.hexdigest()[:16]
@@ -114,6 +119,9 @@ def main():
     torch.cuda.set_stream(stream)
 
     wl = dict(workloads.WORKLOADS[args.workload])
+    if "model" in wl:
+        bench_paper_model(args, wl, torch, lbf, workloads, stream)
+        return
     L = wl.pop("L")
     wl.pop("steps")
     wl.pop("storage", None)
@@ -204,6 +212,147 @@ def main():
         result["cpu_baseline"] = cpu_baseline(L, wl)
 
     print(json.dumps(result), flush=True)
+
+
+PAPER_MODEL = {
+    # model: (lattice name, dimensions, populations, its two kernels per step)
+    "eq": ("D3Q19", 3, 19, ("k_density", "k_meq_collide")),
+    "d2q9": ("D2Q9", 2, 9, ("k2_density", "k2_collide")),
+}
+PAPER_MODEL_SOURCES = {"eq": ("lbfss_device.hpp", "lbfss_step.hpp", "lbfss_meq.hpp"),
+                       "d2q9": ("lbfss_d2q9.hpp",)}
+
+
+def read_step_traffic(model, workload):
+    """HBM bytes per step (both kernels) of a paper-model workload from its
+    committed counter summary, or None if absent or taken on other code."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{PAPER_MODEL[model][3][1]}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    b = re.search(r"traffic_bytes_per_step:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_source_hash(names=PAPER_MODEL_SOURCES[model]):
+        return None
+    return float(b.group(1))
+
+
+def bench_paper_model(args, wl, torch, lbf, workloads, stream):
+    """The paper's own model (GL pressure in the equilibrium, noise with the
+    local sound speed): on D3Q19 (LB_EQ_PRESSURE) or on D2Q9 (the lb2_*
+    calls).  A step is a density pass and a collide pass; the roofline is
+    taken over the pair, with the step's algorithmic bytes (populations read
+    once and written once: 152 B per D3Q19 site, 72 B per D2Q9 site)."""
+    model = wl.pop("model")
+    lattice, dim, q, kernels = PAPER_MODEL[model]
+    L = wl.pop("L")
+    wl.pop("steps")
+    every = wl.pop("sample_every", args.sample_every)
+    N = L ** dim
+    log(f"[bench] {args.workload}: the paper's model on {lattice}, L = {L}, sample every {every}")
+    if args.calibrate_copy:
+        x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    def make(sample_every):
+        if model == "eq":
+            sim = lbf.Sim(L, workloads.SEED, storage=args.storage, sample_every=sample_every,
+                          eq_pressure=True, **wl)
+            sim.set_plan("split", (0, 0, 0), 20)
+            return sim
+        return lbf.Sim2D(L, workloads.SEED, sample_every=sample_every, **wl)
+
+    sim = make(every)
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mlups = N * args.steps / dt / 1e6
+    log(f"[bench] {args.steps} steps in {dt:.3f} s: {mlups:.0f} MLUPS")
+    if args.kernel_only:
+        print(json.dumps({"metric": "MLUPS", "value": mlups, "steps": args.steps}))
+        return
+    del sim
+
+    # the step's two kernels without sampling, HIP events on their stream
+    ksim = make(0)
+    ksim.step(40)
+    ksim.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nk = 400
+    e0.record(stream)
+    ksim.step(nk)
+    e1.record(stream)
+    e1.synchronize()
+    ksim.sync()
+    del ksim
+    ms_per_step = e0.elapsed_time(e1) / nk
+    bps = 2 * q * 4
+    achieved = bps * N / (ms_per_step * 1e-3) / 1e9
+    log(f"[bench] {' + '.join(kernels)}: {ms_per_step * 1e3:.1f} us per step, {achieved:.0f} GB/s algorithmic")
+    copy_gbs = device_copy_gbs(torch, stream)
+    name = f"the paper's model on {lattice} {L}^{dim} ({args.workload})"
+    result = {
+        "metric": f"MLUPS {lattice} fluctuating step of the paper's model (GL pressure in the equilibrium)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "L": L, "sites": N, "storage": "fp32", "sample_every": every,
+                   "params": {k: wl[k] for k in ("a", "b", "kappa", "rho_c", "kT", "tau")},
+                   "plan": "density pass + collide pass" + (", graphs of 20 steps" if model == "eq" else "")},
+        "roofline": {"bound": "hbm", "kernel": " + ".join(kernels), "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": read_step_traffic(model, args.workload), "bytes_per_site": bps,
+                     "us_per_step": round(ms_per_step * 1e3, 2), "device_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline_paper_model(model, L, wl)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline_paper_model(model, L, wl, min_seconds=10.0, max_steps=200):
+    """The NumPy oracle of the paper's model timed on one host thread: whole
+    steps of the workload's lattice for D2Q9, of a 64^3 lattice for D3Q19
+    (the oracle's cost per site does not depend on the size; 256^3 would
+    take about a minute per step)."""
+    from threadpoolctl import threadpool_limits
+    if model == "eq":
+        from oracle import d3q19_meq as M
+        Ls, sites = 64, 64 ** 3
+    else:
+        from oracle import d2q9 as M
+        Ls, sites = L, L ** 2
+    log(f"[bench] cpu baseline: oracle of the paper's model, lattice {Ls}, 1 thread, >= {min_seconds:.0f} s")
+    with threadpool_limits(limits=1):
+        orc = M.Sim(Ls, 20120221, **wl)
+        steps = 0
+        t0 = time.perf_counter()
+        while steps < max_steps:
+            orc.step(1)
+            steps += 1
+            if time.perf_counter() - t0 >= min_seconds:
+                break
+        dt = time.perf_counter() - t0
+    shape = f"{Ls}^3" if model == "eq" else f"{Ls}^2"
+    return {"value": round(steps * sites / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} FP64 steps of a {shape} lattice ({steps * sites} site updates, {dt:.1f} s; "
+                      "NumPy, BLAS limited to one thread)"}
 
 
 def device_copy_gbs(torch, stream, nbytes=1 << 30, reps=5):

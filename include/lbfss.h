@@ -362,6 +362,11 @@ typedef struct {
 int lb2_create(int L, const lb2_params *p, uint64_t seed, lb2_sim **out);
 int lb2_step(lb2_sim *s, int64_t n);   /* asynchronous */
 int lb2_sync(lb2_sim *s);
+/* Order all later device work of the handle on hip_stream (a hipStream_t;
+ * NULL selects the handle's own stream), as lb_set_stream.  Synchronises
+ * the previous stream; the caller keeps ownership of hip_stream, which must
+ * outlive its use by the handle. */
+int lb2_set_stream(lb2_sim *s, void *hip_stream);
 /* rho (L^2), j ([2][L^2]) and f ([9][L^2]) of the current state; any may be
  * NULL; caller-owned FP64 buffers; synchronises. */
 int lb2_fields(lb2_sim *s, double *rho, double *j, double *f);

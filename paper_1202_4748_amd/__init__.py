@@ -27,8 +27,8 @@ EXPORTS = ("lb_create", "lb_create_batch", "lb_step", "lb_sync", "lb_moments", "
            "lb_set_populations", "lb_reset_moments", "lb_set_stream", "lb_set_allocator",
            "lb_set_plan", "lb_get_plan", "lb_tune", "lb_info", "lb_destroy", "lb_strerror",
            "lb_histogram", "lb_hist_estimates", "lb_sk3_shells", "lb_sk3", "lb_oz_fit",
-           "lb2_create", "lb2_step", "lb2_sync", "lb2_fields", "lb2_set_populations", "lb2_spectra",
-           "lb2_reset_spectra", "lb2_destroy")
+           "lb2_create", "lb2_step", "lb2_sync", "lb2_set_stream", "lb2_fields", "lb2_set_populations",
+           "lb2_spectra", "lb2_reset_spectra", "lb2_destroy")
 
 
 class Params(ctypes.Structure):
@@ -139,6 +139,7 @@ def lib():
     L.lb2_create.argtypes = [i32, ctypes.POINTER(Params2), ctypes.c_uint64, ctypes.POINTER(vp)]
     L.lb2_step.argtypes = [vp, ctypes.c_int64]
     L.lb2_sync.argtypes = [vp]
+    L.lb2_set_stream.argtypes = [vp, vp]
     L.lb2_fields.argtypes = [vp, dp, dp, dp]
     L.lb2_set_populations.argtypes = [vp, dp]
     L.lb2_spectra.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp, dp, dp]
@@ -388,6 +389,11 @@ class Sim2D:
         h = ctypes.c_void_p()
         _check(L_.lb2_create(self.L, ctypes.byref(p), ctypes.c_uint64(seed), ctypes.byref(h)), "lb2_create")
         self._h = h
+        if _use_torch():
+            import torch
+            cs = torch.cuda.current_stream().cuda_stream
+            if cs:  # as Sim: torch's current stream unless it is the legacy default one
+                _check(L_.lb2_set_stream(self._h, ctypes.c_void_p(cs)), "lb2_set_stream")
 
     def __del__(self):
         h = getattr(self, "_h", None)

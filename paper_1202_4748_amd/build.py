@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "lbfss.hip")
 DEPS = [os.path.join(HERE, "csrc", f) for f in
         ("lbfss_device.hpp", "lbfss_step.hpp", "lbfss_sample.hpp", "lbfss_fused.hpp", "lbfss_sk3.hpp",
-         "lbfss_d2q9.hpp")] + \
+         "lbfss_d2q9.hpp", "lbfss_meq.hpp")] + \
        [os.path.join(ROOT, "include", "lbfss.h")]
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "liblbfss.so")

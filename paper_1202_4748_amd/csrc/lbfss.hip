@@ -1326,7 +1326,7 @@ struct lb2_sim {
     int L = 0;
     lb2_params P{};
     D2Desc D{};
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr, own_stream = nullptr;
     Allocator alloc;
     std::vector<void *> blocks;
     float *pop[2] = {nullptr, nullptr};
@@ -1354,7 +1354,7 @@ void lb2_destroy(lb2_sim *s) {
         if (s->alloc.free_) s->alloc.free_(p, s->alloc.ctx);
         else (void)hipFree(p);
     }
-    if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
 }
 
@@ -1373,7 +1373,8 @@ int lb2_create(int L, const lb2_params *p, uint64_t seed, lb2_sim **out) {
         lb2_destroy(s);
         return code;
     };
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) return fail(LB_EDEVICE);
+    if (hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking) != hipSuccess) return fail(LB_EDEVICE);
+    s->stream = s->own_stream;
     const double gam = 1.0 - 1.0 / p->tau;
     s->D.L = L;
     s->D.a = (float)p->a;
@@ -1440,10 +1441,22 @@ int lb2_step(lb2_sim *s, int64_t n) {
         if (s->P.sample_every > 0 && s->t % s->P.sample_every == 0) {
             hipLaunchKernelGGL(k2_snap, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->pop[cur ^ 1],
                                s->d_snap);
-            hipLaunchKernelGGL(k2_dft_rows, dim3((unsigned)(3 * s->L)), dim3(kBlock), 0, s->stream, s->L,
-                               (const double *)s->d_snap, (const double *)s->d_twid, s->d_X);
-            hipLaunchKernelGGL(k2_dft_cols, dim3(nb), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
-                               (const double *)s->d_twid, s->d_acc);
+            const unsigned lines = (unsigned)(3 * s->L);
+            if ((s->L & (s->L - 1)) == 0) {  // power of two: FFTs
+                int logL = 0;
+                while ((1 << logL) < s->L) ++logL;
+                hipLaunchKernelGGL(k2_fft_rows, dim3(lines), dim3(kBlock), 0, s->stream, s->L, logL,
+                                   (const double *)s->d_snap, (const double *)s->d_twid, s->d_X);
+                hipLaunchKernelGGL(k2_fft_cols, dim3(lines), dim3(kBlock), 0, s->stream, s->L, logL, s->d_X,
+                                   (const double *)s->d_twid);
+                hipLaunchKernelGGL(k2_spec_acc, dim3(nb), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
+                                   s->d_acc);
+            } else {
+                hipLaunchKernelGGL(k2_dft_rows, dim3(lines), dim3(kBlock), 0, s->stream, s->L,
+                                   (const double *)s->d_snap, (const double *)s->d_twid, s->d_X);
+                hipLaunchKernelGGL(k2_dft_cols, dim3(nb), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
+                                   (const double *)s->d_twid, s->d_acc);
+            }
             s->n_samples += 1;
         }
     }
@@ -1453,6 +1466,13 @@ int lb2_step(lb2_sim *s, int64_t n) {
 int lb2_sync(lb2_sim *s) {
     if (!s) return LB_EINVAL;
     return check2(s);
+}
+
+int lb2_set_stream(lb2_sim *s, void *hip_stream) {
+    if (!s) return LB_EINVAL;
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return LB_EDEVICE;
+    s->stream = hip_stream ? (hipStream_t)hip_stream : s->own_stream;
+    return LB_OK;
 }
 
 int lb2_fields(lb2_sim *s, double *rho, double *j, double *f) {

@@ -342,4 +342,79 @@ k2_dft_cols(int L, const double2 *__restrict__ X, const double *__restrict__ twi
     acc[4 * N + o] += (tr * tr + ti * ti) * inv;
 }
 
+// Power-of-two L: the same transforms as radix-2 FFTs, O(L^2 log L) per
+// sample instead of O(L^3).  One line of L complex values per workgroup in
+// LDS, loaded in bit-reversed order, then log2 L butterfly stages with the
+// twiddles e^{-2 pi i k / L} (k = j L / len for the stage of length len).
+__device__ __forceinline__ void k2_fft_line(double2 *buf, int L, const double *__restrict__ twid) {
+    for (int len = 2; len <= L; len <<= 1) {
+        const int half = len >> 1, step = L / len;
+        for (int b = threadIdx.x; b < L / 2; b += kBlock) {
+            const int grp = b / half, j = b - grp * half;
+            const int i0 = grp * len + j, i1 = i0 + half;
+            const double c = twid[j * step], sn = twid[L + j * step];
+            const double2 u = buf[i0], v = buf[i1];
+            const double tr = v.x * c + v.y * sn, ti = v.y * c - v.x * sn;  // v e^{-i theta}
+            buf[i0] = make_double2(u.x + tr, u.y + ti);
+            buf[i1] = make_double2(u.x - tr, u.y - ti);
+        }
+        __syncthreads();
+    }
+}
+
+// Row FFTs X_c[y][kx] of the snapshot: one workgroup per (channel, row).
+__global__ void __launch_bounds__(kBlock)
+k2_fft_rows(int L, int logL, const double *__restrict__ v, const double *__restrict__ twid,
+            double2 *__restrict__ X) {
+    __shared__ double2 buf[2048];
+    const int64_t r = blockIdx.x;  // channel * L + y
+    for (int x = threadIdx.x; x < L; x += kBlock)
+        buf[__brev((unsigned)x) >> (32 - logL)] = make_double2(v[r * L + x], 0.0);
+    __syncthreads();
+    k2_fft_line(buf, L, twid);
+    for (int kx = threadIdx.x; kx < L; kx += kBlock) X[r * L + kx] = buf[kx];
+}
+
+// Column FFTs in place: X_c[ky][kx] from X_c[y][kx], one workgroup per
+// (channel, kx).
+__global__ void __launch_bounds__(kBlock)
+k2_fft_cols(int L, int logL, double2 *__restrict__ X, const double *__restrict__ twid) {
+    __shared__ double2 buf[2048];
+    const int64_t N = (int64_t)L * L;
+    const int ch = blockIdx.x / L, kx = blockIdx.x - ch * L;
+    double2 *col = X + ch * N + kx;
+    for (int y = threadIdx.x; y < L; y += kBlock) buf[__brev((unsigned)y) >> (32 - logL)] = col[(int64_t)y * L];
+    __syncthreads();
+    k2_fft_line(buf, L, twid);
+    for (int ky = threadIdx.x; ky < L; ky += kBlock) col[(int64_t)ky * L] = buf[ky];
+}
+
+// Accumulation of the spectra from the transformed channels, one thread per
+// (ky, kx): the same sums as the direct transform's.
+__global__ void __launch_bounds__(kBlock)
+k2_spec_acc(int L, const double2 *__restrict__ X, double *__restrict__ acc) {
+    const int64_t N = (int64_t)L * L;
+    const int64_t o = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (o >= N) return;
+    const int ky = (int)(o / L), kx = (int)(o - (int64_t)ky * L);
+    double re[3], im[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const double2 v = X[(int64_t)ch * N + o];
+        re[ch] = v.x;
+        im[ch] = v.y;
+    }
+    const double inv = 1.0 / (double)N;
+    const int mx = kx <= L / 2 ? kx : kx - L, my = ky <= L / 2 ? ky : ky - L;
+    const double kn = sqrt((double)mx * mx + (double)my * my);
+    const double hx = kn > 0 ? mx / kn : 0.0, hy = kn > 0 ? my / kn : 0.0;
+    const double pr = hx * re[1] + hy * re[2], pi = hx * im[1] + hy * im[2];
+    const double tr = -hy * re[1] + hx * re[2], ti = -hy * im[1] + hx * im[2];
+    acc[o] += (re[0] * re[0] + im[0] * im[0]) * inv;
+    acc[N + o] += (re[1] * re[1] + im[1] * im[1]) * inv;
+    acc[2 * N + o] += (re[2] * re[2] + im[2] * im[2]) * inv;
+    acc[3 * N + o] += (pr * pr + pi * pi) * inv;
+    acc[4 * N + o] += (tr * tr + ti * ti) * inv;
+}
+
 }  // namespace lbfss

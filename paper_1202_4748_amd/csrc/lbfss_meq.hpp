@@ -67,6 +67,24 @@ __host__ __device__ constexpr int meq_norm36(int a) {
     return s;
 }
 
+// Both transforms as compile-time tables, so that the unrolled loops are
+// plain constant-coefficient multiply-adds: the forward weights 36 w_q e_a(c_q)
+// (integers) and the back-transform coefficients e_a(c_q) / N_a.
+struct MeqTables {
+    int fwd[Q][Q];     // [a][q]
+    float back[Q][Q];  // [q][a]
+};
+__host__ __device__ constexpr MeqTables meq_tables() {
+    MeqTables t{};
+    for (int a = 0; a < Q; ++a)
+        for (int q = 0; q < Q; ++q) {
+            const int e = meq_basis(a, q);
+            t.fwd[a][q] = meq_w36(q) * e;
+            t.back[q][a] = e == 0 ? 0.0f : (float)e * (36.0f / (float)meq_norm36(a));
+        }
+    return t;
+}
+
 template <typename T, bool SNAP>
 __global__ void __launch_bounds__(kBlock)
 k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T *__restrict__ pop,
@@ -88,15 +106,14 @@ k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T
     // model are O(1) (its rest state keeps the mass on the rest population),
     // and FP32-rounded weights would bias the density of every site the same
     // way each step
+    constexpr MeqTables tab = meq_tables();
     float m[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         float acc = 0.0f;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int c = meq_w36(q) * meq_basis(a, q);
-            if (c != 0) acc += (float)c * f[q];
-        }
+        for (int q = 0; q < Q; ++q)
+            if (tab.fwd[a][q] != 0) acc += (float)tab.fwd[a][q] * f[q];
         m[a] = acc / 36.0f;
     }
     const float dr = m[0];
@@ -181,10 +198,8 @@ k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T
     for (int q = 0; q < Q; ++q) {
         float v = m[0];
 #pragma unroll
-        for (int a = 1; a < Q; ++a) {
-            const int e = meq_basis(a, q);
-            if (e != 0) v += ((float)e * (36.0f / (float)meq_norm36(a))) * m[a];
-        }
+        for (int a = 1; a < Q; ++a)
+            if (tab.back[q][a] != 0.0f) v += tab.back[q][a] * m[a];
         Store<T>::st(out + (int64_t)q * d.N, s, v);
     }
 }

@@ -45,3 +45,33 @@ def test_source_hash_ignores_comments_only():
     c = "int f(int x) { return 3 * x; }\n"
     assert bench.code_of(a) == bench.code_of(b)
     assert bench.code_of(a) != bench.code_of(c)
+
+
+def test_paper_model_traffic_only_for_its_own_sources(tmp_path, monkeypatch):
+    """The per-step traffic of the paper's-model workloads is keyed by the
+    hash of that model's kernel sources (not the force model's)."""
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    h_eq = bench.kernel_source_hash(names=bench.PAPER_MODEL_SOURCES["eq"])
+    h_2d = bench.kernel_source_hash(names=bench.PAPER_MODEL_SOURCES["d2q9"])
+    assert len({h_eq, h_2d, bench.kernel_source_hash()}) == 3
+    (prof / "traffic_k_meq_collide_d3q19_256_eq.md").write_text(
+        f"traffic_bytes_per_step: 4.1e+09\nsource_hash: {h_eq}\n")
+    (prof / "traffic_k2_collide_d2q9_2048.md").write_text(
+        f"traffic_bytes_per_step: 5.2e+08\nsource_hash: {h_eq}\n")  # another model's hash
+    real = bench.kernel_source_hash
+    csrc = os.path.join(ROOT, "paper_1202_4748_amd", "csrc")
+    monkeypatch.setattr(bench, "kernel_source_hash",
+                        lambda csrc_=None, names=bench.STEP_KERNEL_SOURCES: real(csrc, names))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.read_step_traffic("eq", "d3q19_256_eq") == 4.1e9
+    assert bench.read_step_traffic("d2q9", "d2q9_2048") is None
+    assert bench.read_step_traffic("d2q9", "d2q9_256") is None  # no summary
+
+
+def test_paper_model_workloads_are_complete():
+    import workloads
+    for name, wl in workloads.WORKLOADS.items():
+        if "model" in wl:
+            assert wl["model"] in bench.PAPER_MODEL, name
+            assert {"L", "steps", "a", "b", "kappa", "rho_c", "kT", "tau", "init_sigma"} <= set(wl), name

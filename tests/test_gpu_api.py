@@ -87,3 +87,31 @@ def test_stream_and_allocator_do_not_change_results():
     assert np.array_equal(f_a, f_ref)
     assert np.array_equal(f_b, f_ref)
     assert m_b["mass"] == m_ref["mass"] and m_b["levels"] == m_ref["levels"]
+
+
+def test_d2q9_stream_does_not_change_results():
+    """The D2Q9 handle (lb2_set_stream): on its own stream, on a PyTorch side
+    stream, and moved from the side stream back to its own half way, with the
+    spectra sampled: identical populations and spectra."""
+    import torch
+    lbf = require_gpu()
+    L, seed, steps = 24, 43, 18
+    prm = dict(a=0.03, b=0.5, kappa=0.01, rho_c=1.0, kT=1e-5, tau=0.8, init_sigma=0.02, sample_every=3)
+    say("d2q9 own stream")
+    ref = lbf.Sim2D(L, seed, **prm)
+    ref.step(steps)
+    f_ref = ref.fields(f=True)["f"]
+    s_ref = ref.spectra()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        say("d2q9 torch side stream, back to its own after half the steps")
+        b = lbf.Sim2D(L, seed, **prm)
+        b.step(steps // 2)
+    assert lbf.lib().lb2_set_stream(b._h, None) == lbf.LB_OK  # synchronises the side stream first
+    b.step(steps - steps // 2)
+    f_b = b.fields(f=True)["f"]
+    s_b = b.spectra()
+    assert np.array_equal(f_b, f_ref)
+    assert s_b["n_samples"] == s_ref["n_samples"] == steps // 3
+    for k in ("S", "Jx", "Jy"):
+        assert np.array_equal(s_b[k], s_ref[k]), k

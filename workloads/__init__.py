@@ -22,6 +22,12 @@ WORKLOADS = {
     "d3q19_256": dict(L=256, steps=5000, **MODEL),
     # 512^3 precision variant
     "d3q19_512_fp16": dict(L=512, steps=2000, storage="fp16", **MODEL),
+    # the paper's own model (GL pressure in the equilibrium, local-sound-speed
+    # noise) with the same parameters: on D3Q19 at 256^3, and on D2Q9 at the
+    # paper's lattice size 256^2 and at the largest the library takes
+    "d3q19_256_eq": dict(L=256, steps=5000, model="eq", **MODEL),
+    "d2q9_256": dict(L=256, steps=5000, model="d2q9", **MODEL),
+    "d2q9_2048": dict(L=2048, steps=1000, model="d2q9", **MODEL),
 }
 
 
