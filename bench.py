@@ -215,18 +215,32 @@ def main():
 
 
 PAPER_MODEL = {
-    # model: (lattice name, dimensions, populations, its two kernels per step)
-    "eq": ("D3Q19", 3, 19, ("k_density", "k_meq_collide")),
-    "d2q9": ("D2Q9", 2, 9, ("k2_density", "k2_collide")),
+    # model: (lattice name, dimensions, populations)
+    "eq": ("D3Q19", 3, 19),
+    "d2q9": ("D2Q9", 2, 9),
 }
-PAPER_MODEL_SOURCES = {"eq": ("lbfss_device.hpp", "lbfss_step.hpp", "lbfss_meq.hpp"),
+PAPER_MODEL_SOURCES = {"eq": ("lbfss_device.hpp", "lbfss_step.hpp", "lbfss_fused.hpp", "lbfss_meq.hpp"),
                        "d2q9": ("lbfss_d2q9.hpp",)}
 
 
-def read_step_traffic(model, workload):
-    """HBM bytes per step (both kernels) of a paper-model workload from its
-    committed counter summary, or None if absent or taken on other code."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{PAPER_MODEL[model][3][1]}_{workload}.md")
+def paper_model_kernels(model, plan):
+    """The kernels of one step of the paper's model under a plan."""
+    if model == "d2q9":
+        return ("k2_density", "k2_collide")
+    if plan["kernel"] == 3:
+        return ("k_meq_staged",)
+    return ("k_density", "k_meq_collide")
+
+
+def plan_text(plan):
+    return f"{KERNEL_NAMES[plan['kernel']]}:{plan['tile_x']}:{plan['tile_y']}:{plan['tile_z']}"
+
+
+def read_step_traffic(model, workload, kernels, plan=None):
+    """HBM bytes per step of a paper-model workload from its committed
+    counter summary, or None if absent, taken on other code or (D3Q19) on
+    another kernel or tile."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernels[-1]}_{workload}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -234,17 +248,22 @@ def read_step_traffic(model, workload):
     b = re.search(r"traffic_bytes_per_step:\s*([0-9.eE+]+)", text)
     if not m or not b or m.group(1) != kernel_source_hash(names=PAPER_MODEL_SOURCES[model]):
         return None
+    if plan is not None:
+        t = re.search(r"plan (\w+:\d+:\d+:\d+)", text)
+        if not t or t.group(1) != plan_text(plan):
+            return None
     return float(b.group(1))
 
 
 def bench_paper_model(args, wl, torch, lbf, workloads, stream):
     """The paper's own model (GL pressure in the equilibrium, noise with the
-    local sound speed): on D3Q19 (LB_EQ_PRESSURE) or on D2Q9 (the lb2_*
-    calls).  A step is a density pass and a collide pass; the roofline is
-    taken over the pair, with the step's algorithmic bytes (populations read
-    once and written once: 152 B per D3Q19 site, 72 B per D2Q9 site)."""
+    local sound speed): on D3Q19 (LB_EQ_PRESSURE; the rows kernel
+    k_meq_staged or the density and collide passes) or on D2Q9 (the lb2_*
+    calls: a density and a collide pass).  The roofline is taken over the
+    step's kernels with the step's algorithmic bytes (populations read once
+    and written once: 152 B per D3Q19 site, 72 B per D2Q9 site)."""
     model = wl.pop("model")
-    lattice, dim, q, kernels = PAPER_MODEL[model]
+    lattice, dim, q = PAPER_MODEL[model]
     L = wl.pop("L")
     wl.pop("steps")
     every = wl.pop("sample_every", args.sample_every)
@@ -257,15 +276,26 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
         torch.cuda.synchronize()
         del x, y
 
-    def make(sample_every):
-        if model == "eq":
-            sim = lbf.Sim(L, workloads.SEED, storage=args.storage, sample_every=sample_every,
-                          eq_pressure=True, **wl)
-            sim.set_plan("split", (0, 0, 0), 20)
-            return sim
-        return lbf.Sim2D(L, workloads.SEED, sample_every=sample_every, **wl)
+    def make(sample_every, plan=None):
+        if model == "d2q9":
+            return lbf.Sim2D(L, workloads.SEED, sample_every=sample_every, **wl)
+        sim = lbf.Sim(L, workloads.SEED, storage=args.storage, sample_every=sample_every, eq_pressure=True, **wl)
+        if plan is not None:
+            sim.set_plan(KERNEL_NAMES[plan["kernel"]], (plan["tile_x"], plan["tile_y"], plan["tile_z"]),
+                         plan["graph_steps"])
+        return sim
 
     sim = make(every)
+    plan = None
+    if model == "eq":
+        if args.plan:
+            k, tx, ty, tz, g = args.plan.split(":")
+            sim.set_plan(k, (int(tx), int(ty), int(tz)), int(g))
+        elif not args.no_tune and not args.kernel_only:
+            sim.tune(steps=10)
+        plan = sim.plan()
+        log(f"[bench] plan {plan}")
+    kernels = paper_model_kernels(model, plan)
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -281,8 +311,8 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
         return
     del sim
 
-    # the step's two kernels without sampling, HIP events on their stream
-    ksim = make(0)
+    # the step's kernels without sampling, HIP events on their stream
+    ksim = make(0, None if plan is None else dict(plan, graph_steps=max(plan["graph_steps"], 20)))
     ksim.step(40)
     ksim.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -314,10 +344,10 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
         "data": "synthetic",
         "config": {"workload": name, "L": L, "sites": N, "storage": "fp32", "sample_every": every,
                    "params": {k: wl[k] for k in ("a", "b", "kappa", "rho_c", "kT", "tau")},
-                   "plan": "density pass + collide pass" + (", graphs of 20 steps" if model == "eq" else "")},
+                   "plan": plan if plan is not None else "density pass + collide pass"},
         "roofline": {"bound": "hbm", "kernel": " + ".join(kernels), "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": read_step_traffic(model, args.workload), "bytes_per_site": bps,
+                     "traffic": read_step_traffic(model, args.workload, kernels, plan), "bytes_per_site": bps,
                      "us_per_step": round(ms_per_step * 1e3, 2), "device_copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
     }

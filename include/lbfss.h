@@ -86,8 +86,11 @@ enum {
                          * M_16,16 = 3 - 3 c_s^2 in units of 3 rho kT (1/tau)(2 - 1/tau),
                          * c_s^2 = rho (a + 3 b (rho - rho_c)^2); c_s^2 >= 1/2 with kT > 0
                          * raises LB_EUNSTABLE.  Mass and momentum are conserved exactly.
-                         * Split plan only; FP32 storage only (at rest this model keeps
-                         * nearly all mass on the rest population, so the stored
+                         * Plans: LB_KERNEL_SPLIT (a density pass and a collide pass) or
+                         * LB_KERNEL_ROWS (one z-marching pass with a one-site density
+                         * halo; tiles (64,4), (32,8), (16,16), (64,8), (32,16)); the two
+                         * give identical results.  FP32 storage only (at rest this model
+                         * keeps nearly all mass on the rest population, so the stored
                          * deviations are O(1)); not with LB_FORCE_OFF; equal in a batch. */
 };
 
@@ -157,7 +160,8 @@ typedef struct {
 
 /* launch plans (results do not depend on the plan) */
 enum {
-    LB_KERNEL_SPLIT = 0,  /* density pass, chemical-potential pass, collide pass */
+    LB_KERNEL_SPLIT = 0,  /* density pass, chemical-potential pass, collide pass (with
+                           * LB_EQ_PRESSURE: density pass, collide pass) */
     LB_KERNEL_FUSED = 1,  /* one z-marching pass, density halo in LDS, pulls in registers */
     LB_KERNEL_STAGED = 2, /* as FUSED, the next plane's pulls staged asynchronously in LDS
                            * (FP32 storage; FP16 handles run FUSED) */
@@ -170,7 +174,8 @@ typedef struct {
     int32_t kernel;      /* LB_KERNEL_SPLIT, _FUSED, _STAGED or _ROWS */
     int32_t tile_x;      /* fused: tile edge along x; (tile_x, tile_y) in {(32,8), (16,16),
                           * (16,8), (64,4), (64,8)}, (64,4) not staged, (64,8) rows only;
-                          * clamped to L */
+                          * with LB_EQ_PRESSURE rows only, in {(64,4), (32,8), (16,16),
+                          * (64,8), (32,16)}; clamped to L */
     int32_t tile_y;      /* fused: tile edge along y */
     int32_t tile_z;      /* fused: planes marched by one workgroup */
     int32_t graph_steps; /* > 0: capture this many steps (rounded up to even) in a
@@ -183,9 +188,10 @@ typedef struct lb_sim lb_sim; /* opaque, owned by the library */
 /* One periodic L^3 lattice (L >= 4).  Initial state: rho = rho_c +
  * init_sigma g with g the first Box-Muller normal of Philox call
  * (site, 0, 1 << 16, 0), u = 0, f_i = w_i rho.  *out receives the handle.
- * Initial plan: LB_KERNEL_ROWS where every L allows it (else FUSED); when
- * the largest L is at least 128, on 64 x 4 tiles in three z slabs (FP32) or
- * 64 x 8 tiles in six (FP16), else on 32 x 8 tiles; direct launches
+ * Initial plan: LB_KERNEL_ROWS where every L allows it (else FUSED, or SPLIT
+ * with LB_EQ_PRESSURE); when the largest L is at least 128, on 64 x 4 tiles
+ * in three z slabs (FP32; eight with LB_EQ_PRESSURE) or 64 x 8 tiles in six
+ * (FP16), else on 32 x 8 tiles; direct launches
  * (lb_set_plan and lb_tune change it; results do not depend on it).
  * Errors: LB_EINVAL for L < 4, L > 1024, tau <= 1/2, kT < 0, kappa < 0,
  * b < 0, rho_c <= 0, init_sigma < 0, bad storage, flags, sample_every < 0,

@@ -631,6 +631,7 @@ inline std::vector<std::array<int, 3>> fused_tile_candidates(const std::vector<R
             c.push_back({64, 8, tz});
             c.push_back({32, 8, tz});
             c.push_back({16, 16, tz});
+            c.push_back({32, 16, tz});  // taken by the paper's model only
         }
     if (maxL < 16) c.push_back({16, 16, maxL});
     return c;

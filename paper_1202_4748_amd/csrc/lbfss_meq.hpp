@@ -24,7 +24,7 @@
 // gives the matrix of Eq. (lbnoise)); it exists for c_s^2 < 1/2.
 #pragma once
 
-#include "lbfss_step.hpp"
+#include "lbfss_fused.hpp"
 
 namespace lbfss {
 
@@ -85,27 +85,21 @@ __host__ __device__ constexpr MeqTables meq_tables() {
     return t;
 }
 
-template <typename T, bool SNAP>
-__global__ void __launch_bounds__(kBlock)
-k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T *__restrict__ pop,
-              T *__restrict__ pop_out, const float *__restrict__ drho, const uint64_t *__restrict__ step, int koff,
-              int *__restrict__ err, float *__restrict__ snap) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= total) return;
-    const int r = find_rep(desc, nrep, g);
-    const RepDesc &d = desc[r];
-    const int64_t s = g - d.site_off;
-    const Nbr n(s, d.L);
-    float f[Q];
-    pull(pop + Q * d.site_off, d.N, n, f);
-    if constexpr (SNAP) write_snapshot(snap, total, g, f);
-
-    // moments of the stored deviations r_q = f_q / w_q - rho_c: for a >= 1
-    // they are the moments of f; m[0] is rho - rho_c.  Integer weights
-    // (36 w_q e_a) and one correctly rounded division: the deviations of this
-    // model are O(1) (its rest state keeps the mass on the rest population),
-    // and FP32-rounded weights would bias the density of every site the same
-    // way each step
+// The collision of one site.  f holds its 19 pulled values (the stored
+// deviations r_q = f_q / w_q - rho_c) and receives the post-collision ones;
+// at(dx, dy, dz) is the density deviation of the density pass at a
+// neighbour, centre its value at the site; s is the site index in its
+// lattice and t the step (the noise counter).  Returns false where rho or
+// the sound speed leaves its domain.  Both plans call this, so they round
+// alike.
+template <typename F>
+__device__ __forceinline__ bool meq_collide_site(const RepDesc &d, float (&f)[Q], float centre, F &&at, uint32_t s,
+                                                 uint64_t t) {
+    // moments of the stored deviations: for a >= 1 they are the moments of
+    // f; m[0] is rho - rho_c.  Integer weights (36 w_q e_a) and one correctly
+    // rounded division: the deviations of this model are O(1) (its rest
+    // state keeps the mass on the rest population), and FP32-rounded weights
+    // would bias the density of every site the same way each step
     constexpr MeqTables tab = meq_tables();
     float m[Q];
 #pragma unroll
@@ -121,10 +115,8 @@ k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T
     const float jx = m[1], jy = m[2], jz = m[3];
 
     // derivatives of rho from the density pass (isotropic D3Q19 stencils)
-    const float *drp = drho + d.site_off;
-    const NbrAt R{drp, n};
-    const Grad18 gr = grad18(R);
-    const float lap = lap18(drp[s], R);
+    const Grad18 gr = grad18(at);
+    const float lap = lap18(centre, at);
     const float gx = gr.gx, gy = gr.gy, gz = gr.gz;
 
     // thermodynamics and the second moment of the equilibrium
@@ -171,8 +163,7 @@ k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T
         const float L44 = __builtin_amdgcn_sqrtf(fmaxf(5.0f / 3.0f - 3.0f * cs2, 0.0f));
         const float L164 = (3.0f * cs2 - 1.0f) / L44;
         const float L1616 = __builtin_amdgcn_sqrtf(fmaxf(3.0f - 3.0f * cs2 - L164 * L164, 0.0f));
-        const uint64_t t = *step + (uint64_t)koff;
-        const SiteNoise noise{(uint32_t)s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
+        const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
         float gn[16];
 #pragma unroll
         for (int call = 0; call < 4; ++call) {
@@ -190,18 +181,234 @@ k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T
         m[4] += sig * L44 * gn[0];
         m[16] += sig * (L164 * gn[0] + L1616 * gn[12]);
     }
-    if (bad) *err = 1;
 
     // back-transform: r*_q = sum_a e_a(c_q) m*_a / N_a  (m*_0 = rho - rho_c)
-    T *out = pop_out + Q * d.site_off;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         float v = m[0];
 #pragma unroll
         for (int a = 1; a < Q; ++a)
             if (tab.back[q][a] != 0.0f) v += tab.back[q][a] * m[a];
-        Store<T>::st(out + (int64_t)q * d.N, s, v);
+        f[q] = v;
     }
+    return !bad;
+}
+
+// Split plan, pass 2 (after k_density): one site per thread.
+template <typename T, bool SNAP>
+__global__ void __launch_bounds__(kBlock)
+k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T *__restrict__ pop,
+              T *__restrict__ pop_out, const float *__restrict__ drho, const uint64_t *__restrict__ step, int koff,
+              int *__restrict__ err, float *__restrict__ snap) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= total) return;
+    const int r = find_rep(desc, nrep, g);
+    const RepDesc &d = desc[r];
+    const int64_t s = g - d.site_off;
+    const Nbr n(s, d.L);
+    float f[Q];
+    pull(pop + Q * d.site_off, d.N, n, f);
+    if constexpr (SNAP) write_snapshot(snap, total, g, f);
+    const float *drp = drho + d.site_off;
+    const uint64_t t = *step + (uint64_t)koff;
+    if (!meq_collide_site(d, f, drp[s], NbrAt{drp, n}, (uint32_t)s, t)) *err = 1;
+    T *out = pop_out + Q * d.site_off;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) Store<T>::st(out + (int64_t)q * d.N, s, f[q]);
+}
+
+// Rows plan: one z-marching pass per tile, no density pass.  The density
+// needs a halo of one site only (the equilibrium takes grad rho and lap rho,
+// there is no chemical potential), so for each population the workgroup
+// stages the unshifted source rectangle of TY + 2 rows and TX + 8 columns
+// from x0 - 4 (16-byte global-to-LDS loads, aligned when L is a multiple of
+// 4; populations dealt round-robin to the waves).  The value pulled by the
+// site at extended column ex (ex = x - x0 + 1) and row ey is the rectangle
+// entry at row ey, column ex + 3 - cx_q.  Iteration p computes the densities
+// of plane p on the tile and its halo into a ring of three LDS planes,
+// issues the loads of plane p + 1, and collides plane p - 1, whose pulled
+// values waited one iteration in registers; two barriers per plane.  The
+// densities are drho_of of the same values the density pass pulls and the
+// collision is meq_collide_site, so the result equals the split plan's.
+template <int TX, int TY, bool SNAP>
+__global__ void __launch_bounds__(TX * TY)
+k_meq_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const float *__restrict__ pop,
+             float *__restrict__ pop_out, const uint64_t *__restrict__ step, int koff, int *__restrict__ err,
+             float *__restrict__ snap, int64_t total) {
+    constexpr int NT = TX * TY, NW = NT / 64;
+    constexpr int EX = TX + 2, EP = EX * (TY + 2);  // a density plane with its one-site halo
+    constexpr int CH = 4;                           // floats per 16-byte load
+    constexpr int RW = TX + 2 * CH, CW = RW / CH, NL = CW * (TY + 2), NM = (NL + 63) / 64;
+    static_assert(NT % 64 == 0 && 2 * (TX + 2) + 2 * TY <= NT, "one halo site per thread");
+    __shared__ float s_stage[Q][CH * NL];
+    __shared__ float s_rho[3][EP];
+    auto rslot = [](int p) { return (p + 6) % 3; };  // p >= -6
+
+    const FusedTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
+    const RepDesc &d = desc[tl.rep];
+    const int L = d.L;
+    const uint32_t N = (uint32_t)d.N, LL = (uint32_t)(L * L);
+    const float *base = pop + Q * d.site_off;
+    float *obase = pop_out + Q * d.site_off;
+    const uint64_t t = *step + (uint64_t)koff;
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ix = tid % TX, iy = tid / TX;
+    const int nx = tl.nx, ny = tl.ny;
+    const bool inner = ix < nx && iy < ny;
+    const uint32_t site_c = (uint32_t)(tl.x0 + (inner ? ix : 0) + (tl.y0 + (inner ? iy : 0)) * L);
+    const int r_in = (iy + 1) * EX + (ix + 1);
+
+    // the density halo site of this thread: the rows above and below the
+    // tile, then the columns left and right of it
+    const int ew = nx + 2;
+    const bool has_h = tid < 2 * ew + 2 * ny;
+    int hx = 0, hy = 0;
+    if (has_h) {
+        const int h = tid - 2 * ew;
+        if (tid < ew) {
+            hx = tid;
+        } else if (tid < 2 * ew) {
+            hy = ny + 1;
+            hx = tid - ew;
+        } else {
+            hy = 1 + (h >> 1);
+            hx = (h & 1) ? nx + 1 : 0;
+        }
+    }
+    const int r_h = hy * EX + hx;
+
+    // does this wave store populations (then 19 stores may be younger than
+    // the staged loads when it next waits for them)
+    const bool wave_stores = __builtin_amdgcn_readfirstlane((int)(__ballot(inner) != 0)) != 0;
+
+    // the chunks this lane copies, one per 64-lane slice m of the NL chunks of
+    // a population: byte offsets of its column and of its row for the three
+    // y shifts (cy = -1, 0, 1)
+    uint32_t r_col[NM], r_row[NM][3];
+    bool r_on[NM];
+    {
+        const int lane = tid & 63;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int j = m * 64 + lane;
+            r_on[m] = j < NL;
+            const int ey = j / CW, k = j - (j / CW) * CW;
+            r_col[m] = (uint32_t)(((tl.x0 - CH + CH * k) % L + L) % L) * 4u;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                r_row[m][c] = (uint32_t)(((tl.y0 - 1 + ey - (c - 1)) % L + L) % L) * (uint32_t)L * 4u;
+        }
+    }
+    auto issue = [&](int p) __attribute__((always_inline)) {
+        const int zc = wrap_near(p, L);
+        const uint32_t Zc = (uint32_t)zc * LL, Zm = (uint32_t)wrap_dec(zc, L) * LL,
+                       Zp = (uint32_t)wrap_inc(zc, L) * LL;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (q % NW != wave) continue;
+            const int cz = cz_of(q);
+            const char *bq = (const char *)(base + (size_t)q * N + (cz > 0 ? Zm : (cz < 0 ? Zp : Zc)));
+#pragma unroll
+            for (int m = 0; m < NM; ++m)
+                if (r_on[m])
+                    __builtin_amdgcn_global_load_lds((gptr_t)(bq + r_row[m][cy_of(q) + 1] + r_col[m]),
+                                                     (lptr_t)&s_stage[q][m * 64 * CH], 16, 0, 0);
+        }
+    };
+
+    bool bad = false;
+    bool stored_last = false;  // did the previous iteration issue stores (wave-uniform)
+    float A[Q], B[Q];
+    auto body = [&](int p, float(&ld)[Q], float(&cl)[Q]) __attribute__((always_inline)) {
+        // 1. the staged rows of plane p have landed (the stores of the last
+        //    collision, if any, are the only younger memory operations)
+        if (stored_last) __builtin_amdgcn_s_waitcnt(0x4F73);  // vmcnt <= 19
+        else __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt == 0
+        __syncthreads();
+        {
+            float *rs = s_rho[rslot(p)];
+            if (inner) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q) ld[q] = s_stage[q][(iy + 1) * RW + ix + CH - cx_of(q)];
+                rs[r_in] = drho_of(ld);
+            }
+            if (has_h) {
+                float h[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) h[q] = s_stage[q][hy * RW + hx + CH - 1 - cx_of(q)];
+                rs[r_h] = drho_of(h);
+            }
+        }
+        __syncthreads();
+        // 2. prefetch plane p + 1
+        if (p + 1 <= tl.z0 + tl.nz) issue(p + 1);
+        // 3. collision of plane z = p - 1 (densities of z - 1, z, z + 1 in the ring)
+        stored_last = false;
+        const int z = p - 1;
+        if (z >= tl.z0) {
+            stored_last = wave_stores;
+            if (inner) {
+                const float *r0 = s_rho[rslot(z - 1)], *r1 = s_rho[rslot(z)], *r2 = s_rho[rslot(p)];
+                auto at = [&](int dx, int dy, int dz) {
+                    const float *pl = dz < 0 ? r0 : (dz > 0 ? r2 : r1);
+                    return pl[r_in + dy * EX + dx];
+                };
+                const uint32_t s = site_c + (uint32_t)z * LL;
+                if constexpr (SNAP) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
+                bad |= !meq_collide_site(d, cl, r1[r_in], at, s, t);
+                float *oz = obase + (uint32_t)z * LL;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) stb(oz + (size_t)q * N, site_c * 4u, cl[q]);
+            }
+        }
+    };
+
+    const int p0 = tl.z0 - 1, pend = tl.z0 + tl.nz;
+    issue(p0);
+    for (int p = p0; p <= pend; p += 2) {
+        body(p, A, B);
+        if (p + 1 <= pend) body(p + 1, B, A);
+    }
+    if (bad) *err = 1;
+}
+
+// tiles of the rows plan of this model: 256 threads, or 512 (64 x 8,
+// 32 x 16: fewer staged halo rows per site, two workgroups per CU)
+inline bool meq_tile_ok(int tx, int ty) {
+    return (tx == 64 && ty == 4) || (tx == 32 && ty == 8) || (tx == 16 && ty == 16) || (tx == 64 && ty == 8) ||
+           (tx == 32 && ty == 16);
+}
+
+template <bool SNAP>
+void launch_meq_staged_snap(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const float *in, float *out,
+                            const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream, float *snap,
+                            int64_t total) {
+    if (tx == 64 && ty == 4)
+        hipLaunchKernelGGL((k_meq_staged<64, 4, SNAP>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in, out,
+                           step, koff, err, snap, total);
+    else if (tx == 16 && ty == 16)
+        hipLaunchKernelGGL((k_meq_staged<16, 16, SNAP>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in, out,
+                           step, koff, err, snap, total);
+    else if (tx == 64 && ty == 8)
+        hipLaunchKernelGGL((k_meq_staged<64, 8, SNAP>), dim3(n_tiles), dim3(512), 0, stream, desc, tiles, in, out,
+                           step, koff, err, snap, total);
+    else if (tx == 32 && ty == 16)
+        hipLaunchKernelGGL((k_meq_staged<32, 16, SNAP>), dim3(n_tiles), dim3(512), 0, stream, desc, tiles, in, out,
+                           step, koff, err, snap, total);
+    else
+        hipLaunchKernelGGL((k_meq_staged<32, 8, SNAP>), dim3(n_tiles), dim3(256), 0, stream, desc, tiles, in, out,
+                           step, koff, err, snap, total);
+}
+
+// snap: where the step also writes the sample snapshot of its input state,
+// or null
+inline void launch_meq_staged(const RepDesc *desc, const FusedTile *tiles, int n_tiles, const float *in, float *out,
+                              const uint64_t *step, int koff, int *err, int tx, int ty, hipStream_t stream,
+                              float *snap, int64_t total) {
+    if (snap) launch_meq_staged_snap<true>(desc, tiles, n_tiles, in, out, step, koff, err, tx, ty, stream, snap, total);
+    else launch_meq_staged_snap<false>(desc, tiles, n_tiles, in, out, step, koff, err, tx, ty, stream, snap, total);
 }
 
 }  // namespace lbfss

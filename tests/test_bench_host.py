@@ -49,14 +49,21 @@ def test_source_hash_ignores_comments_only():
 
 def test_paper_model_traffic_only_for_its_own_sources(tmp_path, monkeypatch):
     """The per-step traffic of the paper's-model workloads is keyed by the
-    hash of that model's kernel sources (not the force model's)."""
+    hash of that model's kernel sources (not the force model's) and, on
+    D3Q19, by the plan it was measured on."""
     prof = tmp_path / "profiles"
     prof.mkdir()
     h_eq = bench.kernel_source_hash(names=bench.PAPER_MODEL_SOURCES["eq"])
     h_2d = bench.kernel_source_hash(names=bench.PAPER_MODEL_SOURCES["d2q9"])
     assert len({h_eq, h_2d, bench.kernel_source_hash()}) == 3
+    rows = {"kernel": 3, "tile_x": 64, "tile_y": 4, "tile_z": 86, "graph_steps": 20}
+    split = {"kernel": 0, "tile_x": 0, "tile_y": 0, "tile_z": 0, "graph_steps": 20}
+    assert bench.paper_model_kernels("eq", rows) == ("k_meq_staged",)
+    assert bench.paper_model_kernels("eq", split) == ("k_density", "k_meq_collide")
+    (prof / "traffic_k_meq_staged_d3q19_256_eq.md").write_text(
+        f"# HBM traffic: plan rows:64:4:86\ntraffic_bytes_per_step: 2.9e+09\nsource_hash: {h_eq}\n")
     (prof / "traffic_k_meq_collide_d3q19_256_eq.md").write_text(
-        f"traffic_bytes_per_step: 4.1e+09\nsource_hash: {h_eq}\n")
+        f"# HBM traffic: plan split:0:0:0\ntraffic_bytes_per_step: 4.1e+09\nsource_hash: {h_eq}\n")
     (prof / "traffic_k2_collide_d2q9_2048.md").write_text(
         f"traffic_bytes_per_step: 5.2e+08\nsource_hash: {h_eq}\n")  # another model's hash
     real = bench.kernel_source_hash
@@ -64,9 +71,13 @@ def test_paper_model_traffic_only_for_its_own_sources(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash",
                         lambda csrc_=None, names=bench.STEP_KERNEL_SOURCES: real(csrc, names))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.read_step_traffic("eq", "d3q19_256_eq") == 4.1e9
-    assert bench.read_step_traffic("d2q9", "d2q9_2048") is None
-    assert bench.read_step_traffic("d2q9", "d2q9_256") is None  # no summary
+    k_rows, k_split = bench.paper_model_kernels("eq", rows), bench.paper_model_kernels("eq", split)
+    assert bench.read_step_traffic("eq", "d3q19_256_eq", k_rows, rows) == 2.9e9
+    assert bench.read_step_traffic("eq", "d3q19_256_eq", k_rows, dict(rows, tile_z=43)) is None
+    assert bench.read_step_traffic("eq", "d3q19_256_eq", k_split, split) == 4.1e9
+    k2 = bench.paper_model_kernels("d2q9", None)
+    assert bench.read_step_traffic("d2q9", "d2q9_2048", k2) is None
+    assert bench.read_step_traffic("d2q9", "d2q9_256", k2) is None  # no summary
 
 
 def test_paper_model_workloads_are_complete():

@@ -1,9 +1,12 @@
 """The paper's own model on D3Q19 (LB_EQ_PRESSURE: the non-ideal pressure in
 the equilibrium, Sec. III A) on the GPU against its FP64 oracle
-(oracle/d3q19_meq.py), through the C ABI: every step element by element,
-conservation, the batch and plan rules, and equilibrium statistics.
-Tolerances are those of the force model's parity tests (FP32 compute and
-storage against FP64: 1e-5 of the field's largest value)."""
+(oracle/d3q19_meq.py), through the C ABI: every step element by element
+(L = 12 runs the rows kernel k_meq_staged, L = 7 and 10 the split passes),
+the rows plan bit for bit against the split passes (every tile shape,
+partial tiles, samples, graphs, batches, 256^3), conservation, the batch and
+plan rules, and equilibrium statistics.  Tolerances are those of the force
+model's parity tests (FP32 compute and storage against FP64: 1e-5 of the
+field's largest value)."""
 import numpy as np
 import pytest
 
@@ -83,11 +86,18 @@ def test_exact_conservation_and_sampling():
 def test_batch_and_plan_rules():
     lbf = require_gpu()
     sim = lbf.Sim(8, 1, eq_pressure=True, **PRM)
-    assert sim.plan()["kernel"] == lbf.LB_KERNEL_SPLIT
-    for k, t in (("rows", (32, 8, 8)), ("fused", (16, 16, 8)), ("staged", (32, 8, 8))):
+    p = sim.plan()
+    assert (p["kernel"], p["tile_x"], p["tile_y"]) == (lbf.LB_KERNEL_ROWS, 32, 8)
+    for k, t in (("rows", (16, 8, 8)), ("fused", (16, 16, 8)), ("staged", (32, 8, 8))):
         with pytest.raises(lbf.LBError) as e:
             sim.set_plan(k, t)
         assert e.value.code == lbf.LB_EINVAL
+    # the 16-byte row staging needs L a multiple of 4
+    odd = lbf.Sim(10, 1, eq_pressure=True, **PRM)
+    assert odd.plan()["kernel"] == lbf.LB_KERNEL_SPLIT
+    with pytest.raises(lbf.LBError) as e:
+        odd.set_plan("rows", (32, 8, 8))
+    assert e.value.code == lbf.LB_EINVAL
     # a replica evolves in a batch exactly as alone
     Ls, seeds = [8, 12, 6], [4, 5, 6]
     prms = [dict(PRM, eq_pressure=True, a=a) for a in (0.02, 0.03, 0.05)]
@@ -101,6 +111,77 @@ def test_batch_and_plan_rules():
     with pytest.raises(lbf.LBError) as e:
         lbf.Sim.batch([8, 8], [1, 2], [dict(PRM, eq_pressure=True), dict(PRM)])
     assert e.value.code == lbf.LB_EINVAL
+
+
+def _run(lbf, L, seed, plan, steps, sample_every=3, prm=PRM):
+    sim = lbf.Sim(L, seed, eq_pressure=True, sample_every=sample_every, **prm)
+    sim.set_plan(*plan)
+    sim.step(steps)
+    return sim
+
+
+@pytest.mark.parametrize("L,tile", [(12, (32, 8, 5)), (20, (64, 4, 7)), (16, (16, 16, 16)), (24, (64, 4, 24)),
+                                    (36, (16, 16, 9)), (8, (64, 4, 3)), (24, (64, 8, 5)), (40, (32, 16, 13)),
+                                    (68, (64, 8, 23))])
+def test_rows_plan_equals_split(L, tile):
+    """k_meq_staged (full and partial tiles, slabs that do not divide L)
+    against the density and collide passes: the same populations and FP64
+    sample sums bit for bit, with a sample (written by the step kernel)
+    every 3 steps and with graphs."""
+    lbf = require_gpu()
+    say(f"eq-pressure rows {tile} against split, L={L}")
+    prm = dict(PRM, b=2.0)
+    a = _run(lbf, L, 60 + L, ("split", (0, 0, 0)), 17, prm=prm)
+    b = _run(lbf, L, 60 + L, ("rows", tile), 17, prm=prm)
+    c = _run(lbf, L, 60 + L, ("rows", tile, 6), 17, prm=prm)
+    fa = a.fields(f=True)["f"]
+    for o in (b, c):
+        assert np.array_equal(o.fields(f=True)["f"], fa)
+        ma, mo = a.moments(), o.moments()
+        assert ma["n_samples"] == mo["n_samples"] == 5
+        assert ma["mass"] == mo["mass"] and ma["levels"] == mo["levels"]
+        assert np.array_equal(ma["momentum"], mo["momentum"]) and np.array_equal(ma["sk"], mo["sk"])
+
+
+def test_rows_plan_batch():
+    """A batch on the rows plan (tiles of every replica in one launch): each
+    replica as it evolves alone on the split passes."""
+    lbf = require_gpu()
+    Ls, seeds = [8, 12, 16, 20], [4, 5, 6, 7]
+    prms = [dict(PRM, eq_pressure=True, a=a) for a in (0.02, 0.03, 0.05, 0.04)]
+    bat = lbf.Sim.batch(Ls, seeds, prms)
+    assert bat.plan()["kernel"] == lbf.LB_KERNEL_ROWS
+    bat.step(9)
+    for r in range(4):
+        one = lbf.Sim(Ls[r], seeds[r], **prms[r])
+        one.set_plan("split", (0, 0, 0))
+        one.step(9)
+        assert np.array_equal(bat.fields(r, f=True)["f"], one.fields(f=True)["f"]), r
+
+
+def test_rows_plan_256():
+    """256^3 at the bench's parameters: the default plan (rows, 64 x 4 tiles
+    in eight slabs) and the split passes give bit-identical FP64 sample sums
+    (mass, momentum, block levels, axis S(k)) after every step."""
+    lbf = require_gpu()
+    import workloads
+    L, steps = 256, 3
+    prm = dict(workloads.MODEL)
+    say(f"eq-pressure {L}^3: default plan against split, {steps} steps, sample every step")
+    a = lbf.Sim(L, workloads.SEED, eq_pressure=True, sample_every=1, **prm)
+    p = a.plan()
+    assert (p["kernel"], p["tile_x"], p["tile_y"], p["tile_z"]) == (lbf.LB_KERNEL_ROWS, 64, 4, 32)
+    a.step(steps)
+    ma = a.moments()
+    del a
+    b = lbf.Sim(L, workloads.SEED, eq_pressure=True, sample_every=1, **prm)
+    b.set_plan("split", (0, 0, 0))
+    b.step(steps)
+    mb = b.moments()
+    del b
+    assert ma["n_samples"] == mb["n_samples"] == steps
+    assert ma["mass"] == mb["mass"] and ma["levels"] == mb["levels"]
+    assert np.array_equal(ma["momentum"], mb["momentum"]) and np.array_equal(ma["sk"], mb["sk"])
 
 
 def test_unstable_sound_speed_is_flagged():
