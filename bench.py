@@ -220,13 +220,13 @@ PAPER_MODEL = {
     "d2q9": ("D2Q9", 2, 9),
 }
 PAPER_MODEL_SOURCES = {"eq": ("lbfss_device.hpp", "lbfss_step.hpp", "lbfss_fused.hpp", "lbfss_meq.hpp"),
-                       "d2q9": ("lbfss_d2q9.hpp",)}
+                       "d2q9": ("lbfss_device.hpp", "lbfss_fused.hpp", "lbfss_d2q9.hpp")}
 
 
 def paper_model_kernels(model, plan):
     """The kernels of one step of the paper's model under a plan."""
     if model == "d2q9":
-        return ("k2_density", "k2_collide")
+        return ("k2_step_tiled",)
     if plan["kernel"] == 3:
         return ("k_meq_staged",)
     return ("k_density", "k_meq_collide")
@@ -259,7 +259,7 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
     """The paper's own model (GL pressure in the equilibrium, noise with the
     local sound speed): on D3Q19 (LB_EQ_PRESSURE; the rows kernel
     k_meq_staged or the density and collide passes) or on D2Q9 (the lb2_*
-    calls: a density and a collide pass).  The roofline is taken over the
+    calls: one tiled kernel per step).  The roofline is taken over the
     step's kernels with the step's algorithmic bytes (populations read once
     and written once: 152 B per D3Q19 site, 72 B per D2Q9 site)."""
     model = wl.pop("model")
@@ -344,7 +344,7 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
         "data": "synthetic",
         "config": {"workload": name, "L": L, "sites": N, "storage": "fp32", "sample_every": every,
                    "params": {k: wl[k] for k in ("a", "b", "kappa", "rho_c", "kT", "tau")},
-                   "plan": plan if plan is not None else "density pass + collide pass"},
+                   "plan": plan if plan is not None else "one tiled pass (32 x 8 sites per workgroup)"},
         "roofline": {"bound": "hbm", "kernel": " + ".join(kernels), "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": read_step_traffic(model, args.workload, kernels, plan), "bytes_per_site": bps,

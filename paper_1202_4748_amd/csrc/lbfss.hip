@@ -1446,12 +1446,11 @@ int lb2_step(lb2_sim *s, int64_t n) {
     if (!s || n < 0) return LB_EINVAL;
     const int64_t N = (int64_t)s->L * s->L;
     const unsigned nb = (unsigned)ceil_div(N, kBlock);
+    const unsigned tiles = (unsigned)(ceil_div(s->L, K2TX) * ceil_div(s->L, K2TY));
     for (int64_t k = 0; k < n; ++k) {
         const int cur = (int)(s->t & 1);
-        hipLaunchKernelGGL(k2_density, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->pop[cur],
-                           s->d_drho);
-        hipLaunchKernelGGL(k2_collide, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->pop[cur],
-                           s->pop[cur ^ 1], (const float *)s->d_drho, (uint64_t)s->t, s->d_err);
+        hipLaunchKernelGGL(k2_step_tiled, dim3(tiles), dim3(K2TX * K2TY), 0, s->stream, s->D,
+                           (const float *)s->pop[cur], s->pop[cur ^ 1], (uint64_t)s->t, s->d_err);
         s->t += 1;
         if (s->P.sample_every > 0 && s->t % s->P.sample_every == 0) {
             hipLaunchKernelGGL(k2_snap, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->pop[cur ^ 1],

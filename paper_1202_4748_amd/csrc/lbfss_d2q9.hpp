@@ -15,7 +15,7 @@
 // 5 (1,1) 6 (-1,-1) 7 (1,-1) 8 (-1,1).
 #pragma once
 
-#include "lbfss_device.hpp"
+#include "lbfss_fused.hpp"
 
 namespace lbfss {
 
@@ -68,30 +68,14 @@ __device__ __forceinline__ float drho2(const float (&d)[Q2]) {
     return ((d[0] + (d[1] + d[2])) + (d[3] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8]));
 }
 
-// Density deviation of every site (pulled).
-__global__ void __launch_bounds__(kBlock)
-k2_density(D2Desc D, const float *__restrict__ pop, float *__restrict__ drho) {
-    const int L = D.L;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= (int64_t)L * L) return;
-    const int x = (int)(s % L), y = (int)(s / L);
-    float d[Q2];
-    pull2(pop, L, x, y, d);
-    drho[s] = drho2(d);
-}
-
-// One step at every site: pull, moments, equilibrium, relaxation, noise,
-// back-transform; the post-collision deviations go to pop_out unshifted.
-__global__ void __launch_bounds__(kBlock)
-k2_collide(D2Desc D, const float *__restrict__ pop, float *__restrict__ pop_out, const float *__restrict__ drho,
-           uint64_t t, int *__restrict__ err) {
-    const int L = D.L;
-    const int64_t N = (int64_t)L * L;
-    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (s >= N) return;
-    const int x = (int)(s % L), y = (int)(s / L);
-    float d[Q2];
-    pull2(pop, L, x, y, d);
+// The collision of one site: d holds its nine pulled deviations and
+// receives the post-collision ones (stored unshifted: the next step pulls);
+// at(dx, dy) is the density deviation of a neighbour (the same sum drho2 of
+// its pulled values); s is the site index, t the step (the noise counter).
+// Moments, equilibrium, relaxation, noise, back-transform.  Returns false
+// where rho or the noise covariance leaves its domain.
+template <typename F>
+__device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2], F &&at, uint32_t s, uint64_t t) {
     // moment deviations
     float m[Q2];
 #pragma unroll
@@ -104,11 +88,11 @@ k2_collide(D2Desc D, const float *__restrict__ pop, float *__restrict__ pop_out,
     }
     const float dr = drho2(d);  // the same sum as the density array
     const float rho = D.rho_c + dr;
-    // isotropic stencils on the density array
+    // isotropic stencils on the densities of the neighbours
     float gx = 0.0f, gy = 0.0f, lap = 0.0f;
 #pragma unroll
     for (int i = 1; i < Q2; ++i) {
-        const float v = drho[wrap2(x + c2x(i), L) + (int64_t)L * wrap2(y + c2y(i), L)];
+        const float v = at(c2x(i), c2y(i));
         gx += 3.0f * w2(i) * (float)c2x(i) * v;
         gy += 3.0f * w2(i) * (float)c2y(i) * v;
         lap += 6.0f * w2(i) * (v - dr);
@@ -144,8 +128,8 @@ k2_collide(D2Desc D, const float *__restrict__ pop, float *__restrict__ pop_out,
         bad |= !(A > 0.0f) || !(R > 0.0f);
         const float L88 = __builtin_sqrtf(R);
         const float sig = D.noise_amp * __builtin_sqrtf(rho);
-        const Words4 w0 = philox4x32_10((uint32_t)s, (uint32_t)t, 0u, (uint32_t)(t >> 32), D.key0, D.key1);
-        const Words4 w1 = philox4x32_10((uint32_t)s, (uint32_t)t, 1u, (uint32_t)(t >> 32), D.key0, D.key1);
+        const Words4 w0 = philox4x32_10(s, (uint32_t)t, 0u, (uint32_t)(t >> 32), D.key0, D.key1);
+        const Words4 w1 = philox4x32_10(s, (uint32_t)t, 1u, (uint32_t)(t >> 32), D.key0, D.key1);
         const float r0 = bm_radius(uniform01(w0.v[0])), a0 = uniform01(w0.v[1]);
         const float r1 = bm_radius(uniform01(w0.v[2])), a1 = uniform01(w0.v[3]);
         const float r2 = bm_radius(uniform01(w1.v[0])), a2 = uniform01(w1.v[1]);
@@ -159,16 +143,73 @@ k2_collide(D2Desc D, const float *__restrict__ pop, float *__restrict__ pop_out,
         m[7] += sig * 0.816496580927726f * g4;
         m[8] += sig * (L83 * g0 + L88 * g5);
     }
-    // back to populations, stored unshifted (the next step pulls)
+    // back to populations
 #pragma unroll
     for (int i = 0; i < Q2; ++i) {
         float v = 0.0f;
 #pragma unroll
         for (int a = 0; a < Q2; ++a)
             if (e2(a, i) != 0.0f) v += e2(a, i) * (m[a] * (1.0f / n2(a)));
-        pop_out[i * N + s] = w2(i) * v;
+        d[i] = w2(i) * v;
     }
-    if (bad) *err = 1;
+    return !bad;
+}
+
+// One step on a K2TX x K2TY tile per workgroup (tiles at the edges of the
+// lattice are partial, so any L works): every site pulls its nine values,
+// the densities of the tile and of a one-site halo (pulled by the first
+// threads) go to LDS, and after one barrier each site collides with the
+// stencils read there.  The densities are drho2 of the same pulled values
+// wherever they are formed, so the result does not depend on the tiling.
+// Tiles are numbered x fastest and dealt to the XCDs in contiguous runs
+// (xcd_tile), so the halo pulls of a tile find its neighbours' rows in the
+// same L2.
+constexpr int K2TX = 32, K2TY = 8;
+__global__ void __launch_bounds__(K2TX * K2TY)
+k2_step_tiled(D2Desc D, const float *__restrict__ pop, float *__restrict__ pop_out, uint64_t t,
+              int *__restrict__ err) {
+    constexpr int EX = K2TX + 2;
+    static_assert(2 * (K2TX + 2) + 2 * K2TY <= K2TX * K2TY, "one halo site per thread");
+    __shared__ float s_rho[EX * (K2TY + 2)];
+    const int L = D.L;
+    const int64_t N = (int64_t)L * L;
+    const int ntx = (L + K2TX - 1) / K2TX;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % ntx) * K2TX, y0 = (tile / ntx) * K2TY;
+    const int nx = min(K2TX, L - x0), ny = min(K2TY, L - y0);
+    const int tid = threadIdx.x, ix = tid % K2TX, iy = tid / K2TX;
+    const bool inner = ix < nx && iy < ny;
+    const int r_in = (iy + 1) * EX + ix + 1;
+    float d[Q2];
+    if (inner) {
+        pull2(pop, L, x0 + ix, y0 + iy, d);
+        s_rho[r_in] = drho2(d);
+    }
+    // halo: the rows above and below the tile, then the columns beside it
+    const int ew = nx + 2;
+    if (tid < 2 * ew + 2 * ny) {
+        int hx = 0, hy = 0;
+        if (tid < ew) {
+            hx = tid;
+        } else if (tid < 2 * ew) {
+            hy = ny + 1;
+            hx = tid - ew;
+        } else {
+            const int h = tid - 2 * ew;
+            hy = 1 + (h >> 1);
+            hx = (h & 1) ? nx + 1 : 0;
+        }
+        float h[Q2];
+        pull2(pop, L, wrap2(x0 - 1 + hx, L), wrap2(y0 - 1 + hy, L), h);
+        s_rho[hy * EX + hx] = drho2(h);
+    }
+    __syncthreads();
+    if (!inner) return;
+    const uint32_t s = (uint32_t)(x0 + ix) + (uint32_t)L * (uint32_t)(y0 + iy);
+    const bool ok = k2_collide_site(D, d, [&](int dx, int dy) { return s_rho[r_in + dy * EX + dx]; }, s, t);
+#pragma unroll
+    for (int i = 0; i < Q2; ++i) pop_out[i * N + s] = d[i];
+    if (!ok) *err = 1;
 }
 
 // Initial state: rho = rho_c + sigma0 g (generator domain 1, call 0), u = 0,

@@ -64,7 +64,7 @@ def test_paper_model_traffic_only_for_its_own_sources(tmp_path, monkeypatch):
         f"# HBM traffic: plan rows:64:4:86\ntraffic_bytes_per_step: 2.9e+09\nsource_hash: {h_eq}\n")
     (prof / "traffic_k_meq_collide_d3q19_256_eq.md").write_text(
         f"# HBM traffic: plan split:0:0:0\ntraffic_bytes_per_step: 4.1e+09\nsource_hash: {h_eq}\n")
-    (prof / "traffic_k2_collide_d2q9_2048.md").write_text(
+    (prof / "traffic_k2_step_tiled_d2q9_2048.md").write_text(
         f"traffic_bytes_per_step: 5.2e+08\nsource_hash: {h_eq}\n")  # another model's hash
     real = bench.kernel_source_hash
     csrc = os.path.join(ROOT, "paper_1202_4748_amd", "csrc")
