@@ -39,6 +39,25 @@ def test_every_step_against_oracle(L):
     say(f"  worst relative error {worst:.2e}")
 
 
+@pytest.mark.parametrize("L", [40, 36, 256])
+def test_tiled_step_against_oracle(L):
+    """Lattices of several 32 x 8 tiles with partial ones at the edges (40:
+    two tiles across x, the second 8 wide; 36: a last row of tiles 4 high)
+    and the paper's 256^2 (256 tiles dealt to the XCDs in runs): 10 steps
+    against the oracle, every step."""
+    lbf = require_gpu()
+    say(f"d2q9 tiled parity L={L}")
+    g = _sim(lbf, L, 11, **PRM)
+    o = D.Sim(L, 11, **PRM)
+    for t in range(10):
+        g.step(1)
+        o.step(1)
+        st = g.fields(f=True)
+        rho_o, j_o = o.fields()
+        e = (rel_err(st["rho"], rho_o), rel_err(st["j"], j_o), rel_err(st["f"], o.f))
+        assert max(e) < 1e-5, (L, t + 1, e)
+
+
 def test_mass_and_momentum_conserved():
     lbf = require_gpu()
     L = 32
