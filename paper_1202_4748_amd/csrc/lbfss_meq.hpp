@@ -1,8 +1,9 @@
 // The paper's own model on the D3Q19 lattice (Sec. III A): the Ginzburg-
 // Landau thermodynamics carried by a modified equilibrium instead of a body
 // force, BGK relaxation with one tau, and thermal noise whose covariance
-// depends on the local sound speed.  A split step: the density pass of the
-// force model, then one collide pass per site.
+// depends on the local sound speed.  Two plans with the same arithmetic:
+// the split plan (the density pass of the force model, then k_meq_collide)
+// and the rows plan (k_meq_staged, one z-marching pass per tile).
 //
 // Equilibrium (moments of f in the weight-orthogonal basis of the force
 // model): rho, j, the second moment
