@@ -184,6 +184,31 @@ def test_rows_plan_256():
     assert np.array_equal(ma["momentum"], mb["momentum"]) and np.array_equal(ma["sk"], mb["sk"])
 
 
+@pytest.mark.timeout(900)
+def test_256_against_oracle():
+    """256^3 at the bench's parameters, the default plan (the rows kernel on
+    64 x 4 tiles in eight slabs): the first step against the FP64 oracle
+    over the whole lattice (under a minute of host time)."""
+    lbf = require_gpu()
+    import workloads
+    L = 256
+    prm = dict(workloads.MODEL)
+    say(f"eq-pressure {L}^3, default plan, 1 step")
+    sim = lbf.Sim(L, workloads.SEED, eq_pressure=True, **prm)
+    p = sim.plan()
+    assert (p["kernel"], p["tile_x"], p["tile_y"]) == (lbf.LB_KERNEL_ROWS, 64, 4)
+    sim.step(1)
+    got = sim.fields(rho=True, j=True, f=True)
+    del sim
+    say("  oracle 256^3, 1 step (under a minute)")
+    orc = OM.Sim(L, workloads.SEED, **prm)
+    orc.step(1)
+    rho_o, j_o = orc.fields()
+    e = (rel_err(got["rho"], rho_o), rel_err(got["j"], j_o), rel_err(got["f"], orc.f))
+    say(f"  rel errors rho/j/f {e}")
+    assert max(e) <= TOL32
+
+
 def test_unstable_sound_speed_is_flagged():
     """c_s^2 >= 1/2 leaves the noise covariance without a real factor: with
     kT > 0 the step raises the sticky LB_EUNSTABLE."""
