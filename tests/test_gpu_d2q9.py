@@ -39,17 +39,17 @@ def test_every_step_against_oracle(L):
     say(f"  worst relative error {worst:.2e}")
 
 
-@pytest.mark.parametrize("L", [40, 36, 256])
-def test_tiled_step_against_oracle(L):
+@pytest.mark.parametrize("L,steps", [(40, 10), (36, 10), (256, 10), (2048, 2)])
+def test_tiled_step_against_oracle(L, steps):
     """Lattices of several 32 x 8 tiles with partial ones at the edges (40:
-    two tiles across x, the second 8 wide; 36: a last row of tiles 4 high)
-    and the paper's 256^2 (256 tiles dealt to the XCDs in runs): 10 steps
-    against the oracle, every step."""
+    two tiles across x, the second 8 wide; 36: a last row of tiles 4 high),
+    the paper's 256^2 (256 tiles dealt to the XCDs in runs) and the largest
+    lattice, 2048^2 (16384 tiles): every step against the oracle."""
     lbf = require_gpu()
-    say(f"d2q9 tiled parity L={L}")
+    say(f"d2q9 tiled parity L={L}, {steps} steps")
     g = _sim(lbf, L, 11, **PRM)
     o = D.Sim(L, 11, **PRM)
-    for t in range(10):
+    for t in range(steps):
         g.step(1)
         o.step(1)
         st = g.fields(f=True)
