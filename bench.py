@@ -344,7 +344,7 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
         "data": "synthetic",
         "config": {"workload": name, "L": L, "sites": N, "storage": "fp32", "sample_every": every,
                    "params": {k: wl[k] for k in ("a", "b", "kappa", "rho_c", "kT", "tau")},
-                   "plan": plan if plan is not None else "one tiled pass (32 x 8 sites per workgroup)"},
+                   "plan": plan if plan is not None else "one tiled pass (64 x 4 sites per workgroup)"},
         "roofline": {"bound": "hbm", "kernel": " + ".join(kernels), "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": read_step_traffic(model, args.workload, kernels, plan), "bytes_per_site": bps,

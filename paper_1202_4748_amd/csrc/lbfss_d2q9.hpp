@@ -163,8 +163,8 @@ __device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2],
 // wherever they are formed, so the result does not depend on the tiling.
 // Tiles are numbered x fastest and dealt to the XCDs in contiguous runs
 // (xcd_tile), so the halo pulls of a tile find its neighbours' rows in the
-// same L2.
-constexpr int K2TX = 32, K2TY = 8;
+// same L2.  64 x 4 tiles: 3% faster than 32 x 8 at 2048^2, 16 x 16 12% slower.
+constexpr int K2TX = 64, K2TY = 4;
 __global__ void __launch_bounds__(K2TX * K2TY)
 k2_step_tiled(D2Desc D, const float *__restrict__ pop, float *__restrict__ pop_out, uint64_t t,
               int *__restrict__ err) {

@@ -39,12 +39,13 @@ def test_every_step_against_oracle(L):
     say(f"  worst relative error {worst:.2e}")
 
 
-@pytest.mark.parametrize("L,steps", [(40, 10), (36, 10), (256, 10), (2048, 2)])
+@pytest.mark.parametrize("L,steps", [(100, 10), (38, 10), (256, 10), (2048, 2)])
 def test_tiled_step_against_oracle(L, steps):
-    """Lattices of several 32 x 8 tiles with partial ones at the edges (40:
-    two tiles across x, the second 8 wide; 36: a last row of tiles 4 high),
-    the paper's 256^2 (256 tiles dealt to the XCDs in runs) and the largest
-    lattice, 2048^2 (16384 tiles): every step against the oracle."""
+    """Lattices of several 64 x 4 tiles with partial ones at the edges (100:
+    two tiles across x, the second 36 wide; 38: one partial tile across x
+    and a last row of tiles 2 high), the paper's 256^2 (256 tiles dealt to
+    the XCDs in runs) and the largest lattice, 2048^2 (16384 tiles): every
+    step against the oracle."""
     lbf = require_gpu()
     say(f"d2q9 tiled parity L={L}, {steps} steps")
     g = _sim(lbf, L, 11, **PRM)
