@@ -18,10 +18,13 @@ Also reported on the same line:
                 same 96 replicas run one after another (same seeds and steps,
                 so the results are identical).
 
---workload d3q19_256_eq | d2q9_256 | d2q9_2048 times the paper's own model
-(the GL pressure in the equilibrium) instead, on D3Q19 or on D2Q9, with its
-own JSON line: the roofline over its density and collide passes and the
-NumPy oracle of that model on one host thread.
+  paper_model   short runs of the paper's own model (the GL pressure in the
+                equilibrium) on D3Q19 256^3 and D2Q9 256^2 and 2048^2, each
+                on its default plan with its roofline.
+
+--workload d3q19_256_eq | d2q9_256 | d2q9_2048 times one of those alone, with
+its own JSON line: the tuned plan (D3Q19), the roofline over its step
+kernels and the NumPy oracle of that model on one host thread.
 """
 import argparse
 import hashlib
@@ -100,6 +103,8 @@ def main():
                     help="only run warmup + timed steps (for profiler runs)")
     ap.add_argument("--plan", default=None,
                     help="fixed launch plan kernel:tx:ty:tz:graph_steps (kernel split|fused|staged|rows)")
+    ap.add_argument("--no-paper-model", action="store_true",
+                    help="leave out the short runs of the paper's own model (D3Q19 and D2Q9)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -120,7 +125,7 @@ def main():
 
     wl = dict(workloads.WORKLOADS[args.workload])
     if "model" in wl:
-        bench_paper_model(args, wl, torch, lbf, workloads, stream)
+        print(json.dumps(bench_paper_model(args, wl, torch, lbf, workloads, stream)), flush=True)
         return
     L = wl.pop("L")
     wl.pop("steps")
@@ -210,6 +215,10 @@ def main():
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(L, wl)
+
+    if not args.no_paper_model:
+        del sim
+        result["paper_model"] = paper_model_summary(args, torch, lbf, workloads, stream)
 
     print(json.dumps(result), flush=True)
 
@@ -307,8 +316,7 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
     mlups = N * args.steps / dt / 1e6
     log(f"[bench] {args.steps} steps in {dt:.3f} s: {mlups:.0f} MLUPS")
     if args.kernel_only:
-        print(json.dumps({"metric": "MLUPS", "value": mlups, "steps": args.steps}))
-        return
+        return {"metric": "MLUPS", "value": mlups, "steps": args.steps}
     del sim
 
     # the step's kernels without sampling, HIP events on their stream
@@ -353,7 +361,26 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_paper_model(model, L, wl)
-    print(json.dumps(result), flush=True)
+    return result
+
+
+def paper_model_summary(args, torch, lbf, workloads, stream):
+    """Short runs of the paper's own model beside the headline: each
+    workload on its default plan, 200 timed steps with a sample every 10,
+    the roofline of its step kernels; no CPU baseline (bench.py --workload
+    <name> gives the full line)."""
+    out = {}
+    for name in ("d3q19_256_eq", "d2q9_256", "d2q9_2048"):
+        sub = argparse.Namespace(**dict(vars(args), workload=name, steps=200, warmup=20, no_tune=True,
+                                        no_cpu_baseline=True, kernel_only=False, plan=None, calibrate_copy=False,
+                                        storage="fp32"))
+        r = bench_paper_model(sub, dict(workloads.WORKLOADS[name]), torch, lbf, workloads, stream)
+        rf = r["roofline"]
+        out[name] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
+                     "sample_every": r["config"]["sample_every"], "plan": r["config"]["plan"],
+                     "kernel": rf["kernel"], "us_per_step": rf["us_per_step"], "achieved": rf["achieved"],
+                     "frac": rf["frac"], "traffic": rf["traffic"]}
+    return out
 
 
 def cpu_baseline_paper_model(model, L, wl, min_seconds=10.0, max_steps=200):
