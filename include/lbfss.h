@@ -190,8 +190,8 @@ typedef struct lb_sim lb_sim; /* opaque, owned by the library */
  * (site, 0, 1 << 16, 0), u = 0, f_i = w_i rho.  *out receives the handle.
  * Initial plan: LB_KERNEL_ROWS where every L allows it (else FUSED, or SPLIT
  * with LB_EQ_PRESSURE); when the largest L is at least 128, on 64 x 4 tiles
- * in three z slabs (FP32; eight with LB_EQ_PRESSURE) or 64 x 8 tiles in six
- * (FP16), else on 32 x 8 tiles; direct launches
+ * in three z slabs (FP32), 64 x 8 tiles in six (FP16) or 64 x 8 tiles in
+ * eight (LB_EQ_PRESSURE), else on 32 x 8 tiles; direct launches
  * (lb_set_plan and lb_tune change it; results do not depend on it).
  * Errors: LB_EINVAL for L < 4, L > 1024, tau <= 1/2, kT < 0, kappa < 0,
  * b < 0, rho_c <= 0, init_sigma < 0, bad storage, flags, sample_every < 0,

@@ -785,10 +785,14 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
             def.tile_x = 64;
             def.tile_y = s->storage == LB_FP16 ? 8 : 4;
             def.tile_z = s->storage == LB_FP16 ? (maxL + 5) / 6 : (maxL + 2) / 3;
-            // the paper's model (k_meq_staged, 37.6 KB of LDS: four workgroups
-            // per CU) in eight slabs: L = 256 gives 2048 tiles, two rounds;
-            // three slabs measured 5% slower, 64 x 8 tiles no faster
-            if (s->eq_pressure) def.tile_z = (maxL + 7) / 8;
+            // the paper's model (k_meq_staged) on 64 x 8 tiles (512 threads,
+            // 62.6 KB of LDS, two workgroups per CU) in eight slabs: as fast
+            // as 64 x 4 tiles with 17% less HBM traffic (reads 1.13x against
+            // 1.57x the algorithmic bytes); three slabs measured 5% slower
+            if (s->eq_pressure) {
+                def.tile_y = 8;
+                def.tile_z = (maxL + 7) / 8;
+            }
         }
     }
     if (lb_set_plan(s, &def) != LB_OK) {

@@ -160,7 +160,7 @@ def test_rows_plan_batch():
 
 
 def test_rows_plan_256():
-    """256^3 at the bench's parameters: the default plan (rows, 64 x 4 tiles
+    """256^3 at the bench's parameters: the default plan (rows, 64 x 8 tiles
     in eight slabs) and the split passes give bit-identical FP64 sample sums
     (mass, momentum, block levels, axis S(k)) after every step."""
     lbf = require_gpu()
@@ -170,7 +170,7 @@ def test_rows_plan_256():
     say(f"eq-pressure {L}^3: default plan against split, {steps} steps, sample every step")
     a = lbf.Sim(L, workloads.SEED, eq_pressure=True, sample_every=1, **prm)
     p = a.plan()
-    assert (p["kernel"], p["tile_x"], p["tile_y"], p["tile_z"]) == (lbf.LB_KERNEL_ROWS, 64, 4, 32)
+    assert (p["kernel"], p["tile_x"], p["tile_y"], p["tile_z"]) == (lbf.LB_KERNEL_ROWS, 64, 8, 32)
     a.step(steps)
     ma = a.moments()
     del a
@@ -187,7 +187,7 @@ def test_rows_plan_256():
 @pytest.mark.timeout(900)
 def test_256_against_oracle():
     """256^3 at the bench's parameters, the default plan (the rows kernel on
-    64 x 4 tiles in eight slabs): the first step against the FP64 oracle
+    64 x 8 tiles in eight slabs): the first step against the FP64 oracle
     over the whole lattice (under a minute of host time)."""
     lbf = require_gpu()
     import workloads
@@ -196,7 +196,7 @@ def test_256_against_oracle():
     say(f"eq-pressure {L}^3, default plan, 1 step")
     sim = lbf.Sim(L, workloads.SEED, eq_pressure=True, **prm)
     p = sim.plan()
-    assert (p["kernel"], p["tile_x"], p["tile_y"]) == (lbf.LB_KERNEL_ROWS, 64, 4)
+    assert (p["kernel"], p["tile_x"], p["tile_y"]) == (lbf.LB_KERNEL_ROWS, 64, 8)
     sim.step(1)
     got = sim.fields(rho=True, j=True, f=True)
     del sim
