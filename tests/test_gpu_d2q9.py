@@ -39,13 +39,14 @@ def test_every_step_against_oracle(L):
     say(f"  worst relative error {worst:.2e}")
 
 
-@pytest.mark.parametrize("L,steps", [(100, 10), (38, 10), (256, 10), (2048, 2)])
+@pytest.mark.parametrize("L,steps", [(100, 10), (38, 10), (256, 10), (2048, 2), (4, 20), (5, 20)])
 def test_tiled_step_against_oracle(L, steps):
     """Lattices of several 64 x 4 tiles with partial ones at the edges (100:
     two tiles across x, the second 36 wide; 38: one partial tile across x
     and a last row of tiles 2 high), the paper's 256^2 (256 tiles dealt to
-    the XCDs in runs) and the largest lattice, 2048^2 (16384 tiles): every
-    step against the oracle."""
+    the XCDs in runs), the largest lattice, 2048^2 (16384 tiles), and the
+    smallest, 4^2 and 5^2 (one tile whose halo wraps onto the lattice):
+    every step against the oracle."""
     lbf = require_gpu()
     say(f"d2q9 tiled parity L={L}, {steps} steps")
     g = _sim(lbf, L, 11, **PRM)

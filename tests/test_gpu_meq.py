@@ -122,7 +122,7 @@ def _run(lbf, L, seed, plan, steps, sample_every=3, prm=PRM):
 
 @pytest.mark.parametrize("L,tile", [(12, (32, 8, 5)), (20, (64, 4, 7)), (16, (16, 16, 16)), (24, (64, 4, 24)),
                                     (36, (16, 16, 9)), (8, (64, 4, 3)), (24, (64, 8, 5)), (40, (32, 16, 13)),
-                                    (68, (64, 8, 23))])
+                                    (68, (64, 8, 23)), (4, (32, 8, 4)), (4, (64, 8, 1))])
 def test_rows_plan_equals_split(L, tile):
     """k_meq_staged (full and partial tiles, slabs that do not divide L)
     against the density and collide passes: the same populations and FP64
