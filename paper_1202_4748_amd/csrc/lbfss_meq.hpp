@@ -69,21 +69,53 @@ __host__ __device__ constexpr int meq_norm36(int a) {
 }
 
 // Both transforms as compile-time tables, so that the unrolled loops are
-// plain constant-coefficient multiply-adds: the forward weights 36 w_q e_a(c_q)
-// (integers) and the back-transform coefficients e_a(c_q) / N_a.
+// plain constant-coefficient multiply-adds.  The velocities come in opposite
+// pairs (q, q + 1) for odd q, and every basis vector is even or odd under
+// c -> -c (odd: the momentum a = 1..3 and the third-order ghosts a = 10..15),
+// so the forward transform works on the nine pair sums (even moments) or
+// differences (odd moments), and the back-transform forms one even and one
+// odd part per pair: r*_q = E + O, r*_(q+1) = E - O.  The forward weights are
+// the integers 36 w_q e_a(c_q); the back-transform coefficients e_a(c_q) / N_a.
+__host__ __device__ constexpr bool meq_odd(int a) { return (a >= 1 && a <= 3) || (a >= 10 && a <= 15); }
 struct MeqTables {
-    int fwd[Q][Q];     // [a][q]
-    float back[Q][Q];  // [q][a]
+    int fwd0[Q];      // 36 w_0 e_a(0), the rest population (0 for odd a)
+    int fwd[Q][9];    // [a][k]: 36 w_q e_a(c_q), q = 2k + 1
+    float back0[Q];   // e_a(0) / N_a
+    float back[9][Q]; // [k][a]: e_a(c_q) / N_a, q = 2k + 1
 };
 __host__ __device__ constexpr MeqTables meq_tables() {
     MeqTables t{};
-    for (int a = 0; a < Q; ++a)
-        for (int q = 0; q < Q; ++q) {
-            const int e = meq_basis(a, q);
-            t.fwd[a][q] = meq_w36(q) * e;
-            t.back[q][a] = e == 0 ? 0.0f : (float)e * (36.0f / (float)meq_norm36(a));
+    for (int a = 0; a < Q; ++a) {
+        const int e0 = meq_basis(a, 0);
+        t.fwd0[a] = meq_w36(0) * e0;
+        t.back0[a] = e0 == 0 ? 0.0f : (float)e0 * (36.0f / (float)meq_norm36(a));
+        for (int k = 0; k < 9; ++k) {
+            const int e = meq_basis(a, 2 * k + 1);
+            t.fwd[a][k] = meq_w36(2 * k + 1) * e;
+            t.back[k][a] = e == 0 ? 0.0f : (float)e * (36.0f / (float)meq_norm36(a));
         }
+    }
     return t;
+}
+// the pairing and the parities the tables rely on
+__host__ __device__ constexpr bool meq_pairs_ok() {
+    for (int k = 0; k < 9; ++k) {
+        const int q = 2 * k + 1, p = q + 1;
+        if (cx_of(p) != -cx_of(q) || cy_of(p) != -cy_of(q) || cz_of(p) != -cz_of(q)) return false;
+        if (meq_w36(p) != meq_w36(q)) return false;
+        for (int a = 0; a < Q; ++a)
+            if (meq_basis(a, p) != (meq_odd(a) ? -1 : 1) * meq_basis(a, q)) return false;
+    }
+    for (int a = 0; a < Q; ++a)
+        if (meq_odd(a) && meq_basis(a, 0) != 0) return false;
+    return true;
+}
+static_assert(meq_pairs_ok(), "opposite velocity pairs and basis parities");
+
+// nu = (tau - 1/2) / 3 of the Galilean correction, Eq. (holdych-cond)
+__device__ __forceinline__ float meq_nu(const RepDesc &d) {
+    const float tau = 1.0f / (1.0f - d.gamma);
+    return (tau - 0.5f) * (1.0f / 3.0f);
 }
 
 // The collision of one site.  f holds its 19 pulled values (the stored
@@ -95,21 +127,30 @@ __host__ __device__ constexpr MeqTables meq_tables() {
 // alike.
 template <typename F>
 __device__ __forceinline__ bool meq_collide_site(const RepDesc &d, float (&f)[Q], float centre, F &&at, uint32_t s,
-                                                 uint64_t t) {
+                                                 uint64_t t, float nu) {
     // moments of the stored deviations: for a >= 1 they are the moments of
-    // f; m[0] is rho - rho_c.  Integer weights (36 w_q e_a) and one correctly
-    // rounded division: the deviations of this model are O(1) (its rest
-    // state keeps the mass on the rest population), and FP32-rounded weights
-    // would bias the density of every site the same way each step
+    // f; m[0] is rho - rho_c.  Integer weights (36 w_q e_a), and for the
+    // conserved moments (rho, j) one correctly rounded division: the
+    // deviations of this model are O(1) (its rest state keeps the mass on
+    // the rest population), and FP32-rounded weights would bias the mass and
+    // momentum of every site the same way each step.  The non-conserved
+    // moments are relaxed and noised; a product with 1/36 serves them.
     constexpr MeqTables tab = meq_tables();
+    float ps[9], pd[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        ps[k] = f[2 * k + 1] + f[2 * k + 2];
+        pd[k] = f[2 * k + 1] - f[2 * k + 2];
+    }
     float m[Q];
 #pragma unroll
     for (int a = 0; a < Q; ++a) {
         float acc = 0.0f;
+        if (tab.fwd0[a] != 0) acc += (float)tab.fwd0[a] * f[0];
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
-            if (tab.fwd[a][q] != 0) acc += (float)tab.fwd[a][q] * f[q];
-        m[a] = acc / 36.0f;
+        for (int k = 0; k < 9; ++k)
+            if (tab.fwd[a][k] != 0) acc += (float)tab.fwd[a][k] * (meq_odd(a) ? pd[k] : ps[k]);
+        m[a] = a < 4 ? acc / 36.0f : acc * (1.0f / 36.0f);
     }
     const float dr = m[0];
     const float rho = d.rho_c + dr;
@@ -127,8 +168,6 @@ __device__ __forceinline__ bool meq_collide_site(const RepDesc &d, float (&f)[Q]
     const float f0 = 0.5f * d.a * dd * dd + 0.25f * d.b * dd * dd * dd * dd;
     const float p0 = rho * (d.a * dd + d.b * dd * dd * dd) - f0;
     const float cs2 = rho * (d.a + 3.0f * d.b * dd * dd);
-    const float tau = 1.0f / (1.0f - d.gamma);
-    const float nu = (tau - 0.5f) * (1.0f / 3.0f);
     const float g2 = gx * gx + gy * gy + gz * gz;
     const float p_iso = p0 - d.kappa * rho * lap - 0.5f * d.kappa * g2;
     const float ug = ux * gx + uy * gy + uz * gz;
@@ -183,14 +222,26 @@ __device__ __forceinline__ bool meq_collide_site(const RepDesc &d, float (&f)[Q]
         m[16] += sig * (L164 * gn[0] + L1616 * gn[12]);
     }
 
-    // back-transform: r*_q = sum_a e_a(c_q) m*_a / N_a  (m*_0 = rho - rho_c)
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    // back-transform: r*_q = sum_a e_a(c_q) m*_a / N_a  (m*_0 = rho - rho_c),
+    // the rest population, then the even and odd parts of each pair
+    {
         float v = m[0];
 #pragma unroll
         for (int a = 1; a < Q; ++a)
-            if (tab.back[q][a] != 0.0f) v += tab.back[q][a] * m[a];
-        f[q] = v;
+            if (tab.back0[a] != 0.0f) v += tab.back0[a] * m[a];
+        f[0] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        float ev = m[0], od = 0.0f;
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+            if (tab.back[k][a] == 0.0f) continue;
+            if (meq_odd(a)) od += tab.back[k][a] * m[a];
+            else ev += tab.back[k][a] * m[a];
+        }
+        f[2 * k + 1] = ev + od;
+        f[2 * k + 2] = ev - od;
     }
     return !bad;
 }
@@ -212,7 +263,7 @@ k_meq_collide(const RepDesc *__restrict__ desc, int nrep, int64_t total, const T
     if constexpr (SNAP) write_snapshot(snap, total, g, f);
     const float *drp = drho + d.site_off;
     const uint64_t t = *step + (uint64_t)koff;
-    if (!meq_collide_site(d, f, drp[s], NbrAt{drp, n}, (uint32_t)s, t)) *err = 1;
+    if (!meq_collide_site(d, f, drp[s], NbrAt{drp, n}, (uint32_t)s, t, meq_nu(d))) *err = 1;
     T *out = pop_out + Q * d.site_off;
 #pragma unroll
     for (int q = 0; q < Q; ++q) Store<T>::st(out + (int64_t)q * d.N, s, f[q]);
@@ -252,6 +303,7 @@ k_meq_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ til
     const float *base = pop + Q * d.site_off;
     float *obase = pop_out + Q * d.site_off;
     const uint64_t t = *step + (uint64_t)koff;
+    const float nu = meq_nu(d);
 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -358,7 +410,7 @@ k_meq_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ til
                 };
                 const uint32_t s = site_c + (uint32_t)z * LL;
                 if constexpr (SNAP) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
-                bad |= !meq_collide_site(d, cl, r1[r_in], at, s, t);
+                bad |= !meq_collide_site(d, cl, r1[r_in], at, s, t, nu);
                 float *oz = obase + (uint32_t)z * LL;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) stb(oz + (size_t)q * N, site_c * 4u, cl[q]);
