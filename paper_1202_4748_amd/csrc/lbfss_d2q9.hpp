@@ -68,6 +68,23 @@ __device__ __forceinline__ float drho2(const float (&d)[Q2]) {
     return ((d[0] + (d[1] + d[2])) + (d[3] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8]));
 }
 
+// Opposite velocities come in pairs (q, q + 1) for q = 1, 3, 5, 7, and each
+// basis vector is even or odd under c -> -c (odd: a = 1, 2, 6, 7), so the
+// transforms work on pair sums and differences (checked at compile time).
+__host__ __device__ constexpr bool k2_odd(int a) { return a == 1 || a == 2 || a == 6 || a == 7; }
+__host__ __device__ constexpr bool k2_pairs_ok() {
+    for (int k = 0; k < 4; ++k) {
+        const int q = 2 * k + 1, p = q + 1;
+        if (c2x(p) != -c2x(q) || c2y(p) != -c2y(q) || w2(p) != w2(q)) return false;
+        for (int a = 0; a < Q2; ++a)
+            if (e2(a, p) != (k2_odd(a) ? -e2(a, q) : e2(a, q))) return false;
+    }
+    for (int a = 0; a < Q2; ++a)
+        if (k2_odd(a) && e2(a, 0) != 0.0f) return false;
+    return true;
+}
+static_assert(k2_pairs_ok(), "opposite velocity pairs and basis parities");
+
 // The collision of one site: d holds its nine pulled deviations and
 // receives the post-collision ones (stored unshifted: the next step pulls);
 // at(dx, dy) is the density deviation of a neighbour (the same sum drho2 of
@@ -76,14 +93,22 @@ __device__ __forceinline__ float drho2(const float (&d)[Q2]) {
 // where rho or the noise covariance leaves its domain.
 template <typename F>
 __device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2], F &&at, uint32_t s, uint64_t t) {
-    // moment deviations
+    // moment deviations, from the rest value and the pair sums (even
+    // moments) or differences (odd moments)
+    float ps[4], pd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ps[k] = d[2 * k + 1] + d[2 * k + 2];
+        pd[k] = d[2 * k + 1] - d[2 * k + 2];
+    }
     float m[Q2];
 #pragma unroll
     for (int a = 0; a < Q2; ++a) {
         float v = 0.0f;
+        if (e2(a, 0) != 0.0f) v += e2(a, 0) * d[0];
 #pragma unroll
-        for (int i = 0; i < Q2; ++i)
-            if (e2(a, i) != 0.0f) v += e2(a, i) * d[i];
+        for (int k = 0; k < 4; ++k)
+            if (e2(a, 2 * k + 1) != 0.0f) v += e2(a, 2 * k + 1) * (k2_odd(a) ? pd[k] : ps[k]);
         m[a] = v;
     }
     const float dr = drho2(d);  // the same sum as the density array
@@ -124,7 +149,8 @@ __device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2],
     if (D.noise_amp > 0.0f) {
         const float A = 4.0f * (2.0f - 3.0f * cs2), C = 12.0f * (cs2 - 1.0f / 3.0f),
                     B = 16.0f * (1.25f - 0.75f * cs2);
-        const float L33 = __builtin_sqrtf(A), L83 = C / L33, R = B - L83 * L83;
+        // L83 scales normals only: the hardware reciprocal serves it
+        const float L33 = __builtin_sqrtf(A), L83 = C * __builtin_amdgcn_rcpf(L33), R = B - L83 * L83;
         bad |= !(A > 0.0f) || !(R > 0.0f);
         const float L88 = __builtin_sqrtf(R);
         const float sig = D.noise_amp * __builtin_sqrtf(rho);
@@ -143,14 +169,29 @@ __device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2],
         m[7] += sig * 0.816496580927726f * g4;
         m[8] += sig * (L83 * g0 + L88 * g5);
     }
-    // back to populations
+    // back to populations: the rest one, then an even and an odd part per pair
+    float mn[Q2];
 #pragma unroll
-    for (int i = 0; i < Q2; ++i) {
+    for (int a = 0; a < Q2; ++a) mn[a] = m[a] * (1.0f / n2(a));
+    {
         float v = 0.0f;
 #pragma unroll
         for (int a = 0; a < Q2; ++a)
-            if (e2(a, i) != 0.0f) v += e2(a, i) * (m[a] * (1.0f / n2(a)));
-        d[i] = w2(i) * v;
+            if (e2(a, 0) != 0.0f) v += e2(a, 0) * mn[a];
+        d[0] = w2(0) * v;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = 2 * k + 1;
+        float ev = 0.0f, od = 0.0f;
+#pragma unroll
+        for (int a = 0; a < Q2; ++a) {
+            if (e2(a, q) == 0.0f) continue;
+            if (k2_odd(a)) od += e2(a, q) * mn[a];
+            else ev += e2(a, q) * mn[a];
+        }
+        d[q] = w2(q) * (ev + od);
+        d[q + 1] = w2(q) * (ev - od);
     }
     return !bad;
 }
