@@ -13,6 +13,9 @@ Also reported on the same line:
                 152 algorithmic bytes per site update (19 FP32 populations
                 read + 19 written), timed with HIP events on its stream, and
                 against a 1 GiB device-to-device copy timed on the same GPU;
+                beside it the HBM traffic and VALU busy fraction from the
+                committed counter summaries (null when those were taken on
+                other code or another plan);
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload;
   batched       the 96-replica finite-size sweep in one handle against the
                 same 96 replicas run one after another (same seeds and steps,
@@ -86,6 +89,25 @@ def read_traffic(kname, workload, storage, plan):
     if (t.group(1), int(t.group(2)), int(t.group(3)), int(t.group(4))) != here:
         return None
     return float(b.group(1))
+
+
+def read_valu_busy(kname, workload, names, plan=None):
+    """VALU busy fraction of a step kernel from its committed counter summary
+    (profiles/valu_<kernel>_<workload>.md), or None if absent, taken on
+    other kernel sources or on another kernel or tile."""
+    path = os.path.join(ROOT, "profiles", f"valu_{kname}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    v = re.search(r"valu_busy:\s*([0-9.]+)", text)
+    if not m or not v or m.group(1) != kernel_source_hash(names=names):
+        return None
+    if plan is not None:
+        t = re.search(r"plan (\w+:\d+:\d+:\d+)", text)
+        if not t or t.group(1) != plan_text(plan):
+            return None
+    return float(v.group(1))
 
 
 def main():
@@ -205,6 +227,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_site": BYTES_PER_SITE[args.storage],
+                     "valu_busy": read_valu_busy(kname, args.workload if args.workload.endswith("_" + args.storage)
+                                                 else f"{args.workload}_{args.storage}", STEP_KERNEL_SOURCES, kplan),
                      "us_per_launch": round(ms_per_launch * 1e3, 2),
                      "device_copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "mass": mom["mass"],
@@ -356,6 +380,8 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
         "roofline": {"bound": "hbm", "kernel": " + ".join(kernels), "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": read_step_traffic(model, args.workload, kernels, plan), "bytes_per_site": bps,
+                     "valu_busy": read_valu_busy(kernels[-1], args.workload, PAPER_MODEL_SOURCES[model], plan)
+                     if len(kernels) == 1 else None,
                      "us_per_step": round(ms_per_step * 1e3, 2), "device_copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
@@ -379,7 +405,7 @@ def paper_model_summary(args, torch, lbf, workloads, stream):
         out[name] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
                      "sample_every": r["config"]["sample_every"], "plan": r["config"]["plan"],
                      "kernel": rf["kernel"], "us_per_step": rf["us_per_step"], "achieved": rf["achieved"],
-                     "frac": rf["frac"], "traffic": rf["traffic"]}
+                     "frac": rf["frac"], "traffic": rf["traffic"], "valu_busy": rf["valu_busy"]}
     return out
 
 

@@ -86,3 +86,24 @@ def test_paper_model_workloads_are_complete():
         if "model" in wl:
             assert wl["model"] in bench.PAPER_MODEL, name
             assert {"L", "steps", "a", "b", "kappa", "rho_c", "kT", "tau", "init_sigma"} <= set(wl), name
+
+
+def test_valu_busy_only_for_the_profiled_sources_and_plan(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    real = bench.kernel_source_hash
+    csrc = os.path.join(ROOT, "paper_1202_4748_amd", "csrc")
+    h = real(csrc, bench.STEP_KERNEL_SOURCES)
+    (prof / "valu_k_fused_staged_d3q19_256_fp32.md").write_text(
+        f"# VALU use: k_fused_staged, plan rows:64:4:86\nvalu_busy: 0.5756\nsource_hash: {h}\n")
+    (prof / "valu_k2_step_tiled_d2q9_2048.md").write_text(f"valu_busy: 0.83\nsource_hash: {h}\n")
+    monkeypatch.setattr(bench, "kernel_source_hash",
+                        lambda csrc_=None, names=bench.STEP_KERNEL_SOURCES: real(csrc, names))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    rows = {"kernel": 3, "tile_x": 64, "tile_y": 4, "tile_z": 86, "graph_steps": 10}
+    assert bench.read_valu_busy("k_fused_staged", "d3q19_256_fp32", bench.STEP_KERNEL_SOURCES, rows) == 0.5756
+    assert bench.read_valu_busy("k_fused_staged", "d3q19_256_fp32", bench.STEP_KERNEL_SOURCES,
+                                dict(rows, tile_z=43)) is None
+    # another model's sources, or no summary
+    assert bench.read_valu_busy("k2_step_tiled", "d2q9_2048", bench.PAPER_MODEL_SOURCES["d2q9"]) is None
+    assert bench.read_valu_busy("k_meq_staged", "d3q19_256_eq", bench.PAPER_MODEL_SOURCES["eq"], rows) is None
