@@ -162,7 +162,7 @@ __device__ __forceinline__ bool meq_collide_site(const RepDesc &d, float (&f)[Q]
     const float gx = gr.gx, gy = gr.gy, gz = gr.gz;
 
     // thermodynamics and the second moment of the equilibrium
-    const float inv_rho = 1.0f / rho;
+    const float inv_rho = __builtin_amdgcn_rcpf(rho);  // hardware reciprocal, 1 ulp (as the force model)
     const float ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
     const float dd = dr;
     const float f0 = 0.5f * d.a * dd * dd + 0.25f * d.b * dd * dd * dd * dd;
@@ -201,7 +201,7 @@ __device__ __forceinline__ bool meq_collide_site(const RepDesc &d, float (&f)[Q]
         bad |= !(cs2 < 0.5f);
         const float sig = d.noise_amp * __builtin_amdgcn_sqrtf(fmaxf(rho, 0.0f));
         const float L44 = __builtin_amdgcn_sqrtf(fmaxf(5.0f / 3.0f - 3.0f * cs2, 0.0f));
-        const float L164 = (3.0f * cs2 - 1.0f) / L44;
+        const float L164 = (3.0f * cs2 - 1.0f) * __builtin_amdgcn_rcpf(L44);  // scales normals only
         const float L1616 = __builtin_amdgcn_sqrtf(fmaxf(3.0f - 3.0f * cs2 - L164 * L164, 0.0f));
         const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
         float gn[16];
