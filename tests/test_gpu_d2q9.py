@@ -104,11 +104,11 @@ def _oracle_spectra(rho, j, L):
             "Jpar": np.abs(par) ** 2 / N, "Jperp": np.abs(perp) ** 2 / N}
 
 
-@pytest.mark.parametrize("L", [12, 16, 64, 256, 512, 1024])
+@pytest.mark.parametrize("L", [12, 16, 64, 256, 512, 1024, 2048])
 def test_spectra_against_oracle_transform(L):
     """The GPU's spectra of its own states equal numpy's FFT of the exported
     fields (the GPU sums the same FP32 state in FP64): direct transforms for
-    L = 12, radix-2 FFTs for the powers of two, up to 1024^2."""
+    L = 12, radix-2 FFTs for the powers of two, up to 2048^2."""
     lbf = require_gpu()
     g = _sim(lbf, L, 8, sample_every=3, **PRM)
     acc = None
