@@ -178,16 +178,24 @@ typedef struct {
                           * (64,8), (32,16)}; clamped to L */
     int32_t tile_y;      /* fused: tile edge along y */
     int32_t tile_z;      /* fused: planes marched by one workgroup */
-    int32_t graph_steps; /* > 0: capture this many steps (rounded up to even) in a
-                          * HIP graph and replay it; 0: launch kernels directly */
+    int32_t graph_steps; /* > 0: capture this many steps in a HIP graph and replay
+                          * it, rounded up to a multiple of the sampling period
+                          * (sample_every, times sk3_stride when set, doubled if odd;
+                          * 2 without sampling); LB_EINVAL if the rounded value
+                          * exceeds 100000; 0: launch kernels directly */
     int32_t reserved;
 } lb_plan;
 
 typedef struct lb_sim lb_sim; /* opaque, owned by the library */
 
-/* One periodic L^3 lattice (L >= 4).  Initial state: rho = rho_c +
+/* One periodic L^3 lattice (L >= 4) of the model of Sec. III A (Eq. (lbe):
+ * BGK relaxation of f towards f^eq plus the noise of Eq. (lbnoise)), with the
+ * Ginzburg-Landau parameters of Sec. II A, Eqs. (fef) and (landau-pot): a, b
+ * and kappa are the r, u and kappa there, rho_c the density about which the
+ * Landau potential is expanded.  Initial state: rho = rho_c +
  * init_sigma g with g the first Box-Muller normal of Philox call
- * (site, 0, 1 << 16, 0), u = 0, f_i = w_i rho.  *out receives the handle.
+ * (site, 0, 1 << 16, 0), u = 0, f_i = w_i rho.  *out receives the handle
+ * (owned by the library until lb_destroy); p is read during the call only.
  * Initial plan: LB_KERNEL_ROWS where every L allows it (else FUSED, or SPLIT
  * with LB_EQ_PRESSURE); when the largest L is at least 128, on 64 x 4 tiles
  * in three z slabs (FP32), 64 x 8 tiles in six (FP16) or 64 x 8 tiles in
@@ -203,13 +211,27 @@ int lb_create(int L, const lb_params *p, uint64_t seed, lb_sim **out);
  * Each replica evolves exactly as it would alone under lb_create. */
 int lb_create_batch(int n, const int *L, const lb_params *p, const uint64_t *seeds, lb_sim **out);
 
-/* Advance every replica by n >= 0 steps (asynchronous on the handle's stream). */
+/* Advance every replica by n >= 0 steps (asynchronous on the handle's stream).
+ * One step is Eq. (lbe) of Sec. III A: the moments rho, j of the pulled
+ * populations (Eq. (mom)), the chemical potential and the force of steps 2-3
+ * of the file preamble, the moment-space collision with the noise of
+ * Eq. (lbnoise) drawn at the current step counter, and streaming; on steps
+ * after which the counter is a multiple of sample_every the observables of
+ * lb_moments are accumulated.  LB_EINVAL for n < 0 or a NULL handle; launch
+ * failures return LB_EDEVICE; instability shows at the next synchronising
+ * call (sticky LB_EUNSTABLE). */
 int lb_step(lb_sim *s, int64_t n);
 
 /* Wait for the handle's work; LB_EUNSTABLE if the sticky flag is set. */
 int lb_sync(lb_sim *s);
 
-/* Accumulated observables of one replica (synchronising).  sk, if not NULL,
+/* Accumulated observables of one replica (synchronising): the block
+ * order-parameter sums of Sec. II B (Eq. (mL) for m over boxes of edge L_b,
+ * from which Eqs. (ML), (chiL), (chiL-lowT) and (CL) are formed; the Binder
+ * ratio <m^4>/<m^2>^2 likewise) and the axis structure factor of Sec. IV A,
+ * Eq. (G-comput), with phi = (rho - rho0)/rho0 of Eq. (op), plus the current
+ * mass and momentum (FP64 sums).  out: caller-owned; LB_EINVAL for a bad
+ * replica index.  sk, if not NULL,
  * receives 3 * n_k doubles: sk[a * n_k + m - 1] = sum over samples of
  * L^-3 |sum_r phi e^{-i k_m r_a}|^2, k_m = 2 pi m / L, axis a = x, y, z.
  * series, if not NULL, receives series_len records (oldest first) of
@@ -287,14 +309,30 @@ typedef struct {
 int lb_oz_fit(lb_sim *sim, int replica, double k_max, int x_lattice, lb_oz_t *out);
 
 /* Current fields of one replica copied to host memory owned by the caller
- * (synchronising); any pointer may be NULL.  rho: L^3 doubles, j: 3 L^3
- * ([3][L^3]), f: 19 L^3 ([19][L^3]) post-streaming populations. */
+ * (synchronising); any pointer may be NULL.  rho and j are the moments of
+ * Eq. (mom) (Sec. III A) of the post-streaming populations, summed in FP64:
+ * rho: L^3 doubles, j: 3 L^3 ([3][L^3]), f: 19 L^3 ([19][L^3]) populations
+ * f_i(r, t) in the velocity order above.  LB_EINVAL for a bad replica,
+ * LB_ENOMEM when the device staging buffers cannot be had. */
 int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f);
 
 /* Replace the populations of one replica by f ([19][L^3] doubles, post-
  * streaming, host memory), rounded to the storage precision.  The step
  * counter and accumulators are kept (synchronising). */
 int lb_set_populations(lb_sim *s, int replica, const double *f);
+
+/* Set the step counter of every replica to t >= 0: the populations held are
+ * then the post-streaming f_i(r, t), and the next step draws the noise of
+ * Eq. (lbnoise) from counters (site, t_lo, call, t_hi), t_lo and t_hi the low
+ * and high 32-bit words of t.  With lb_fields (f) and lb_set_populations this
+ * resumes a run exactly: a handle created with the same L, parameters and
+ * seed, given the populations and step count of another, continues that run
+ * bit for bit (FP32 and FP16 storage round-trip exactly through the FP64
+ * populations).  A sample due on the current state is taken first; the state
+ * at the new step is not sampled (sampling resumes after the next step that
+ * ends on a multiple of sample_every); the accumulators are kept.
+ * Synchronises.  LB_EINVAL for t < 0. */
+int lb_set_step(lb_sim *s, int64_t t);
 
 /* Zero every replica's accumulators, sample count and series. */
 int lb_reset_moments(lb_sim *s);
@@ -326,6 +364,22 @@ int lb_info(lb_sim *s, lb_info_t *out);
 
 /* Release every resource of the handle (NULL is ignored). */
 void lb_destroy(lb_sim *s);
+
+/* The generator of the noise of Eq. (lbnoise) (its Gaussian random
+ * variables), on counters the caller chooses; for testing the step kernels'
+ * random numbers against an independent implementation.  For i < n: ctr[4i..4i+3]
+ * and key[2i..2i+1] (host memory) give the Philox4x32-10 counter and key;
+ * words[4i..4i+3] receives the four output words, uniforms[4i..4i+3] their
+ * uniforms ((w >> 9) + 1/2) 2^-23, normals[4i..4i+3] the Box-Muller pairs
+ * sqrt(-2 ln u0) (cos 2 pi u1, sin 2 pi u1), then the same of (u2, u3), as the
+ * step kernels form them (host memory, caller-owned; any output may be NULL).
+ * The model's counters are (site, t_lo, call | domain << 16, t_hi) with key
+ * (seed_lo, seed_hi): domain 0, calls 0..3 for the collision noise; domain 1,
+ * call 0 at t = 0 for the initial density.  Runs on the current device on a
+ * stream of its own and synchronises.  LB_EINVAL for n < 0, n > 2^24 or NULL
+ * inputs with n > 0; LB_ENOMEM; LB_EDEVICE. */
+int lb_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *words, float *uniforms,
+              float *normals);
 
 /* Static description of an error code. */
 const char *lb_strerror(int code);

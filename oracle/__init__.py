@@ -30,10 +30,10 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB) or (
-            os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
-        _build.build()
-    L = ctypes.CDLL(_build.LIB)
+    path = _build.library()
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+        _build.build(sanitize=path == _build.LIB_SAN)
+    L = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
     u32p = ctypes.POINTER(ctypes.c_uint32)
     L.orc_lattice.argtypes = [ctypes.POINTER(ctypes.c_int), dp, dp, dp]

@@ -27,6 +27,7 @@ EXPORTS = ("lb_create", "lb_create_batch", "lb_step", "lb_sync", "lb_moments", "
            "lb_set_populations", "lb_reset_moments", "lb_set_stream", "lb_set_allocator",
            "lb_set_plan", "lb_get_plan", "lb_tune", "lb_info", "lb_destroy", "lb_strerror",
            "lb_histogram", "lb_hist_estimates", "lb_sk3_shells", "lb_sk3", "lb_oz_fit",
+           "lb_set_step", "lb_philox",
            "lb2_create", "lb2_step", "lb2_sync", "lb2_set_stream", "lb2_fields", "lb2_set_populations",
            "lb2_spectra", "lb2_reset_spectra", "lb2_destroy")
 
@@ -136,6 +137,9 @@ def lib():
     L.lb_sk3_shells.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64), dp, dp]
     L.lb_sk3.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp]
     L.lb_oz_fit.argtypes = [vp, i32, ctypes.c_double, i32, ctypes.POINTER(OzT)]
+    L.lb_set_step.argtypes = [vp, ctypes.c_int64]
+    u32p, fp = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)
+    L.lb_philox.argtypes = [ctypes.c_int64, u32p, u32p, u32p, fp, fp]
     L.lb2_create.argtypes = [i32, ctypes.POINTER(Params2), ctypes.c_uint64, ctypes.POINTER(vp)]
     L.lb2_step.argtypes = [vp, ctypes.c_int64]
     L.lb2_sync.argtypes = [vp]
@@ -283,6 +287,10 @@ class Sim:
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
         _check(lib().lb_set_populations(self._h, replica, _dp(f)), "lb_set_populations")
 
+    def set_step(self, t):
+        """Set the step counter (the populations held are then f(r, t))."""
+        _check(lib().lb_set_step(self._h, int(t)), "lb_set_step")
+
     def moments(self, replica=0, series=False):
         m = MomentsT()
         L = self.Ls[replica]
@@ -373,6 +381,25 @@ class Sim:
         i = InfoT()
         _check(lib().lb_info(self._h, ctypes.byref(i)), "lb_info")
         return {k: getattr(i, k) for k, _ in i._fields_}
+
+
+def philox(ctr, key):
+    """The device generator of the noise on given counters: ctr [n, 4] and key
+    [n, 2] (uint32) -> words [n, 4] (uint32), uniforms [n, 4] and Box-Muller
+    normals [n, 4] (float32), as the step kernels form them (lb_philox)."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    if ctr.shape[0] != key.shape[0]:
+        raise ValueError("ctr and key need the same number of rows")
+    n = ctr.shape[0]
+    words = np.zeros((n, 4), dtype=np.uint32)
+    uni = np.zeros((n, 4), dtype=np.float32)
+    nrm = np.zeros((n, 4), dtype=np.float32)
+    u32p, fp = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)
+    _use_torch()
+    _check(lib().lb_philox(n, ctr.ctypes.data_as(u32p), key.ctypes.data_as(u32p), words.ctypes.data_as(u32p),
+                           uni.ctypes.data_as(fp), nrm.ctypes.data_as(fp)), "lb_philox")
+    return words, uni, nrm
 
 
 class Sim2D:

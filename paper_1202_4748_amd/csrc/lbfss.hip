@@ -31,6 +31,9 @@ Allocator g_alloc;
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// longest step loop captured in one graph
+constexpr int64_t kMaxGraphSteps = 100000;
+
 }  // namespace
 
 struct lb_sim {
@@ -674,6 +677,14 @@ int build_tiles(lb_sim *s, int tx, int ty, int tz) {
     std::vector<FusedTile> tiles;
     if (make_fused_tiles(s->hdesc, tx, ty, tz, tiles) != 0) return LB_EINVAL;
     if (s->d_tiles && s->tiles_for[0] == tx && s->tiles_for[1] == ty && s->tiles_for[2] == tz) return LB_OK;
+    if (s->d_tiles) {
+        // the old table may still be read by queued kernels and captured graphs
+        HIPCHK(hipStreamSynchronize(s->stream));
+        drop_graph(s);
+        dev_release(s, s->d_tiles, sizeof(FusedTile) * std::max<size_t>((size_t)s->n_tiles, 1));
+        s->d_tiles = nullptr;
+        s->n_tiles = 0;
+    }
     int rc = upload(s, &s->d_tiles, tiles);
     if (rc) return rc;
     s->n_tiles = (int)tiles.size();
@@ -1183,11 +1194,14 @@ int lb_set_allocator(void *(*alloc)(size_t, void *), void (*free_)(void *, void 
 
 int lb_set_plan(lb_sim *s, const lb_plan *plan) {
     if (!s || !plan) return LB_EINVAL;
-    if (plan->graph_steps < 0 || plan->graph_steps > 100000) return LB_EINVAL;
+    if (plan->graph_steps < 0) return LB_EINVAL;
     lb_plan p = *plan;
     if (p.graph_steps > 0) {
+        // rounded up to the sampling period (even), at most kMaxGraphSteps
         const int64_t P = graph_period(s);
-        p.graph_steps = (int)(ceil_div(p.graph_steps, P) * P);
+        const int64_t G = ceil_div(p.graph_steps, P) * P;
+        if (G > kMaxGraphSteps) return LB_EINVAL;
+        p.graph_steps = (int)G;
     }
     if (p.kernel == LB_KERNEL_FUSED || p.kernel == LB_KERNEL_STAGED || p.kernel == LB_KERNEL_ROWS) {
         if (s->eq_pressure) {
@@ -1297,6 +1311,24 @@ int lb_tune(lb_sim *s, int steps, lb_plan *best) {
     return check_err(s);
 }
 
+int lb_set_step(lb_sim *s, int64_t t) {
+    if (!s || t < 0) return LB_EINVAL;
+    flush_pending(s);  // a due sample belongs to the state before the change
+    if ((t & 1) != (s->t & 1)) {
+        // the current state sits in buffer (old step & 1); the step kernels
+        // read buffer (step & 1), so the two buffers trade places, and the
+        // captured graphs, which hold the old order, are dropped
+        std::swap(s->pop[0], s->pop[1]);
+        drop_graph(s);
+    }
+    const uint64_t v = (uint64_t)t;
+    HIPCHK(hipMemcpyAsync(s->d_step, &v, sizeof(v), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->t = t;
+    s->pending = false;
+    return check_err(s);
+}
+
 int lb_info(lb_sim *s, lb_info_t *out) {
     if (!s || !out) return LB_EINVAL;
     std::memset(out, 0, sizeof(*out));
@@ -1322,6 +1354,42 @@ void lb_destroy(lb_sim *s) {
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
     delete s;
+}
+
+int lb_philox(int64_t n, const uint32_t *ctr, const uint32_t *key, uint32_t *words, float *uniforms,
+              float *normals) {
+    if (n < 0 || n > kPhiloxMax || (n > 0 && (!ctr || !key))) return LB_EINVAL;
+    if (n == 0) return LB_OK;
+    const size_t in_bytes = sizeof(uint32_t) * 6 * (size_t)n, out_bytes = 12 * sizeof(uint32_t) * (size_t)n;
+    void *buf = nullptr;
+    if (g_alloc.alloc) buf = g_alloc.alloc(in_bytes + out_bytes, g_alloc.ctx);
+    else if (hipMalloc(&buf, in_bytes + out_bytes) != hipSuccess) buf = nullptr;
+    if (!buf) return LB_ENOMEM;
+    uint32_t *d_ctr = (uint32_t *)buf, *d_key = d_ctr + 4 * n, *d_w = d_key + 2 * n;
+    float *d_u = (float *)(d_w + 4 * n), *d_g = d_u + 4 * n;
+    hipStream_t st = nullptr;
+    int rc = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess ? LB_OK : LB_EDEVICE;
+    if (rc == LB_OK && (hipMemcpyAsync(d_ctr, ctr, sizeof(uint32_t) * 4 * n, hipMemcpyHostToDevice, st) ||
+                        hipMemcpyAsync(d_key, key, sizeof(uint32_t) * 2 * n, hipMemcpyHostToDevice, st)))
+        rc = LB_EDEVICE;
+    if (rc == LB_OK) {
+        hipLaunchKernelGGL(k_philox_probe, dim3((unsigned)ceil_div(n, kBlock)), dim3(kBlock), 0, st, n,
+                           (const uint32_t *)d_ctr, (const uint32_t *)d_key, d_w, d_u, d_g);
+        if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
+    }
+    if (rc == LB_OK && words && hipMemcpyAsync(words, d_w, sizeof(uint32_t) * 4 * n, hipMemcpyDeviceToHost, st))
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && uniforms && hipMemcpyAsync(uniforms, d_u, sizeof(float) * 4 * n, hipMemcpyDeviceToHost, st))
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && normals && hipMemcpyAsync(normals, d_g, sizeof(float) * 4 * n, hipMemcpyDeviceToHost, st))
+        rc = LB_EDEVICE;
+    if (st) {
+        if (hipStreamSynchronize(st) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
+        (void)hipStreamDestroy(st);
+    }
+    if (g_alloc.free_) g_alloc.free_(buf, g_alloc.ctx);
+    else (void)hipFree(buf);
+    return rc;
 }
 
 const char *lb_strerror(int code) {

@@ -321,4 +321,30 @@ k_import(const RepDesc d, const double *__restrict__ f, T *__restrict__ pop) {
 
 __global__ void k_add_step(uint64_t *step, int64_t n) { *step += (uint64_t)n; }
 
+// The generator of the noise on caller-given counters: per counter the four
+// Philox4x32-10 words, their uniforms, and the Box-Muller normals of the word
+// pairs (0, 1) and (2, 3) (radius from the even word, angle from the odd one),
+// through the same device functions as the step kernels.
+constexpr int64_t kPhiloxMax = int64_t(1) << 24;
+__global__ void __launch_bounds__(kBlock)
+k_philox_probe(int64_t n, const uint32_t *__restrict__ ctr, const uint32_t *__restrict__ key,
+               uint32_t *__restrict__ words, float *__restrict__ uni, float *__restrict__ nrm) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const Words4 w = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key[2 * i],
+                                   key[2 * i + 1]);
+    float u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        words[4 * i + k] = w.v[k];
+        u[k] = uniform01(w.v[k]);
+        uni[4 * i + k] = u[k];
+    }
+    const float r0 = bm_radius(u[0]), r1 = bm_radius(u[2]);
+    nrm[4 * i] = r0 * cos_rev(u[1]);
+    nrm[4 * i + 1] = r0 * sin_rev(u[1]);
+    nrm[4 * i + 2] = r1 * cos_rev(u[3]);
+    nrm[4 * i + 3] = r1 * sin_rev(u[3]);
+}
+
 }  // namespace lbfss

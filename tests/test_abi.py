@@ -90,3 +90,12 @@ def test_invalid_arguments_rejected_before_device(L):
     P2 = (lbf.Params * 2)(lbf.make_params(sample_every=2, sk3_stride=1), lbf.make_params(sample_every=2))
     assert L.lb_create_batch(2, Ls2, P2, (ctypes.c_uint64 * 2)(1, 2), ctypes.byref(h)) == lbf.LB_EINVAL
     L.lb_destroy(None)
+
+
+def test_new_calls_check_arguments_on_host(L):
+    """lb_philox and lb_set_step reject bad arguments before any HIP call."""
+    assert L.lb_philox(-1, None, None, None, None, None) == lbf.LB_EINVAL
+    assert L.lb_philox(3, None, None, None, None, None) == lbf.LB_EINVAL
+    assert L.lb_philox((1 << 24) + 1, None, None, None, None, None) == lbf.LB_EINVAL
+    assert L.lb_philox(0, None, None, None, None, None) == lbf.LB_OK
+    assert L.lb_set_step(None, 5) == lbf.LB_EINVAL

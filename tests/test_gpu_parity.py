@@ -1,16 +1,18 @@
 """GPU path against the FP64 oracle, element by element, through the C ABI.
 
-Tolerance (FP32 compute and storage against FP64): after every step, for each
-field X in {rho, j, f}: max |X_gpu - X_oracle| / max |X_oracle| <= 1e-5.
+Tolerances (FP32 compute and storage against FP64), after every step:
+- max |X_gpu - X_oracle| / max |X_oracle| <= 1e-5 for X in {rho, j, f} (the
+  field bound of the target, as a fraction of the largest value);
+- || X_gpu - X_oracle ||_2 / || X_oracle - X_rest ||_2 <= DTOL32 for the
+  deviations drho (X_rest the mean density) and f - w_i rho_c: the bound held
+  to the fluctuation itself, which is ~1e-3 of rho.  Measured worst 2.9e-7
+  (16^3, 1000 steps); DTOL32 = 2e-6 keeps a margin of about 7.
 
 FP16 storage rounds each stored deviation r_i = (f_i - w_i rho_c)/w_i
-(|r| <~ 0.1) to 11 significant bits: at most 2^-15 = 3e-5 absolute per
-population and step.  Through sum_i w_i c_i r_i that is <= 1e-5 absolute in a
-momentum component per step (about 3e-4 of max |j| ~ 0.03 at kT = 1e-4), and
-<= 3e-5 in rho (3e-5 of max rho ~ 1).  Momentum is conserved, so these
-roundings random-walk: after n steps the error grows like sqrt(n) times the
-typical (about a third of the worst) step error.  Over 100 steps the FP16
-bounds are 3e-3 for j and 3e-4 for rho and f.
+(|r| <~ 0.1) to 11 significant bits, so the FP16 bounds are set by those
+roundings: measured worst over 100 steps (16^3) rho 2.0e-5, j 3.4e-4, f
+4.3e-5 of the largest value, deviation-relative drho 2.9e-4 and f 2.5e-4;
+each bound below is about 5 times the measured worst.
 """
 import numpy as np
 import pytest
@@ -22,11 +24,22 @@ from gpu_util import dev_rel_err, rel_err, require_gpu, say
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
-TOL16 = {"rho": 3e-4, "j": 3e-3, "f": 3e-4}
+TOL16 = {"rho": 1e-4, "j": 1.5e-3, "f": 2e-4}
+DTOL32 = 2e-6
+DTOL16 = 1.5e-3
 M0 = workloads.MODEL
 
 
-def _compare(sim, orc, tol, where, replica=0):
+def dev_errors(fg, orc):
+    """Deviation-relative errors of drho and of f - w rho_c."""
+    rho_o, _ = orc.fields()
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)[:, None]
+    rest = w * orc.prm.rho_c
+    ef = float(np.linalg.norm(fg["f"] - orc.f) / max(np.linalg.norm(orc.f - rest), 1e-300))
+    return dev_rel_err(fg["rho"], rho_o), ef
+
+
+def _compare(sim, orc, tol, where, replica=0, dtol=None):
     fg = sim.fields(replica, rho=True, j=True, f=True)
     rho_o, j_o = orc.fields()
     e = (rel_err(fg["rho"], rho_o), rel_err(fg["j"], j_o), rel_err(fg["f"], orc.f))
@@ -35,6 +48,10 @@ def _compare(sim, orc, tol, where, replica=0):
     else:
         ok = max(e) <= tol
     assert ok, f"{where}: rel errors rho/j/f = {e}"
+    if dtol is not None:
+        d = dev_errors(fg, orc)
+        assert max(d) <= dtol, f"{where}: deviation-relative errors drho/f = {d}"
+        e = e + d
     return e
 
 
@@ -54,13 +71,32 @@ def test_config0_100_steps(kernel):
     sim = lbf.Sim(16, workloads.SEED, **M0)
     sim.set_plan(kernel, (16, 16, 8))
     orc = oracle.Sim(16, workloads.SEED, **M0)
-    worst = 0.0
+    worst = np.zeros(5)
     for t in range(100):
         sim.step(1)
         orc.step(1)
-        worst = max(worst, max(_compare(sim, orc, TOL32, f"step {t + 1}")))
-    rho_g = sim.fields()["rho"]
-    say(f"  worst field error {worst:.2e}, deviation-relative {dev_rel_err(rho_g, orc.rho()):.2e}")
+        worst = np.maximum(worst, _compare(sim, orc, TOL32, f"step {t + 1}", dtol=DTOL32))
+    say(f"  worst rho/j/f {worst[0]:.2e} {worst[1]:.2e} {worst[2]:.2e}, "
+        f"deviation-relative drho/f {worst[3]:.2e} {worst[4]:.2e}")
+
+
+def test_config0_1000_steps():
+    """The whole 16^3 run of 1000 steps on the default plan with graph replay
+    and sampling every step, checked at steps 1, 10, 100 and 1000."""
+    lbf = require_gpu()
+    say("config0 L=16 1000 steps")
+    sim = lbf.Sim(16, workloads.SEED, sample_every=1, **M0)
+    orc = oracle.Sim(16, workloads.SEED, **M0)
+    done = 0
+    for t in (1, 10, 100, 1000):
+        if t - done >= 8:
+            sim.set_plan("rows", (32, 8, 16), graph_steps=8)
+        sim.step(t - done)
+        orc.step(t - done)
+        done = t
+        e = _compare(sim, orc, TOL32, f"step {t}", dtol=DTOL32)
+        say(f"  step {t}: rho/j/f {e[0]:.2e} {e[1]:.2e} {e[2]:.2e}, drho/f {e[3]:.2e} {e[4]:.2e}")
+    assert sim.moments()["n_samples"] == 1000
 
 
 @pytest.mark.parametrize("L,kernel,tile", [(4, "rows", (16, 16, 4)), (7, "staged", (32, 8, 3)),
@@ -81,7 +117,7 @@ def test_ragged_sizes(L, kernel, tile):
     for t in range(10):
         sim.step(1)
         orc.step(1)
-        _compare(sim, orc, TOL32, f"L={L} step {t + 1}")
+        _compare(sim, orc, TOL32, f"L={L} step {t + 1}", dtol=DTOL32)
 
 
 def test_strong_nonequilibrium_state():
@@ -101,7 +137,7 @@ def test_strong_nonequilibrium_state():
         for t in range(20):
             sim.step(1)
             orc.step(1)
-            _compare(sim, orc, TOL32, f"{kernel} step {t + 1}")
+            _compare(sim, orc, TOL32, f"{kernel} step {t + 1}", dtol=DTOL32)
 
 
 def test_force_off_ideal_gas():
@@ -112,7 +148,7 @@ def test_force_off_ideal_gas():
     orc = oracle.Sim(12, 3, **prm)
     sim.step(20)
     orc.step(20)
-    _compare(sim, orc, TOL32, "force off")
+    _compare(sim, orc, TOL32, "force off", dtol=DTOL32)
 
 
 @pytest.mark.parametrize("kernel", ["split", "rows"])
@@ -122,14 +158,13 @@ def test_fp16_storage(kernel):
     sim = lbf.Sim(16, workloads.SEED, storage="fp16", **M0)
     sim.set_plan(kernel, (32, 8, 5))
     orc = oracle.Sim(16, workloads.SEED, **M0)
-    worst = (0.0, 0.0, 0.0)
+    worst = np.zeros(5)
     for t in range(100):
         sim.step(1)
         orc.step(1)
         if (t + 1) % 10 == 0:
-            e = _compare(sim, orc, TOL16, f"fp16 step {t + 1}")
-            worst = tuple(max(a, b) for a, b in zip(worst, e))
-    say(f"  fp16 worst rel errors rho/j/f = {worst}")
+            worst = np.maximum(worst, _compare(sim, orc, TOL16, f"fp16 step {t + 1}", dtol=DTOL16))
+    say(f"  fp16 worst rel errors rho/j/f = {worst[:3]}, deviation-relative drho/f = {worst[3:]}")
 
 
 def test_plans_bit_identical():
@@ -279,7 +314,7 @@ def test_separate_relaxation_times(kernel):
     for t in range(30):
         sim.step(1)
         orc.step(1)
-        _compare(sim, orc, TOL32, f"step {t + 1}")
+        _compare(sim, orc, TOL32, f"step {t + 1}", dtol=DTOL32)
 
 
 @pytest.mark.parametrize("kernel", ["split", "fused", "rows"])
@@ -320,4 +355,4 @@ def test_degenerate_parameters(name, prm):
     for t in range(10):
         sim.step(1)
         orc.step(1)
-        _compare(sim, orc, TOL32, f"{name} step {t + 1}")
+        _compare(sim, orc, TOL32, f"{name} step {t + 1}", dtol=DTOL32)

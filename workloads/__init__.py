@@ -47,17 +47,17 @@ def sweep_replicas(seeds_per_point=4):
 
 
 def random_populations(L, seed, rho_c=1.0, drho=0.02, u=0.02, neq=0.01):
-    """A generic non-equilibrium state: w_i rho (1 + 3 c.u + ...) plus random
-    non-hydrodynamic parts, [19, L^3] doubles."""
+    """A generic far-from-equilibrium state, [19, L^3] doubles, built from
+    random numbers only: the rest weights times (rho_c + a density field of
+    standard deviation drho + independent per-population parts of standard
+    deviation neq), plus, on each pair of opposite velocities, one random
+    number of standard deviation 6 u added to one and taken from the other
+    (a site momentum of about u per axis)."""
     rng = np.random.default_rng(seed)
     N = L ** 3
-    C = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
-                  (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
-                  (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)], float)
     W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
-    rho = rho_c + drho * rng.standard_normal(N)
-    vel = u * rng.standard_normal((3, N))
-    cu = C @ vel
-    f = W[:, None] * rho * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * np.sum(vel * vel, axis=0))
-    f += neq * W[:, None] * rng.standard_normal((19, N))
+    f = W[:, None] * (rho_c + drho * rng.standard_normal(N)[None, :] + neq * rng.standard_normal((19, N)))
+    odd = 6.0 * u * rng.standard_normal((9, N))
+    f[1::2] += W[1::2, None] * odd   # velocities 1, 3, ..., 17 and their opposites 2, 4, ..., 18
+    f[2::2] -= W[2::2, None] * odd
     return f
