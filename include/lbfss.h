@@ -316,6 +316,18 @@ int lb_oz_fit(lb_sim *sim, int replica, double k_max, int x_lattice, lb_oz_t *ou
  * LB_ENOMEM when the device staging buffers cannot be had. */
 int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f);
 
+/* lb_fields for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same outputs, bit for bit, with the FP64 staging of the exported fields
+ * in a static device array of 2^22 doubles (32 MiB) per GPU, held until the
+ * process ends, instead of per-call allocations.  The requested outputs must
+ * fit it: L^3 ((rho != NULL) + 3 (j != NULL) + 19 (f != NULL)) <= 2^22, else
+ * LB_EINVAL (L <= 56 with f; L <= 101 for rho and j).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other threads,
+ * other handles, other streams) race, so the caller serialises them.
+ * Synchronising; errors as lb_fields. */
+int lb_fields_static(lb_sim *s, int replica, double *rho, double *j, double *f);
+
 /* Replace the populations of one replica by f ([19][L^3] doubles, post-
  * streaming, host memory), rounded to the storage precision.  The step
  * counter and accumulators are kept (synchronising). */

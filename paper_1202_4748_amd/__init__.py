@@ -27,7 +27,7 @@ EXPORTS = ("lb_create", "lb_create_batch", "lb_step", "lb_sync", "lb_moments", "
            "lb_set_populations", "lb_reset_moments", "lb_set_stream", "lb_set_allocator",
            "lb_set_plan", "lb_get_plan", "lb_tune", "lb_info", "lb_destroy", "lb_strerror",
            "lb_histogram", "lb_hist_estimates", "lb_sk3_shells", "lb_sk3", "lb_oz_fit",
-           "lb_set_step", "lb_philox",
+           "lb_set_step", "lb_philox", "lb_fields_static",
            "lb2_create", "lb2_step", "lb2_sync", "lb2_set_stream", "lb2_fields", "lb2_set_populations",
            "lb2_spectra", "lb2_reset_spectra", "lb2_destroy")
 
@@ -138,6 +138,7 @@ def lib():
     L.lb_sk3.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp]
     L.lb_oz_fit.argtypes = [vp, i32, ctypes.c_double, i32, ctypes.POINTER(OzT)]
     L.lb_set_step.argtypes = [vp, ctypes.c_int64]
+    L.lb_fields_static.argtypes = [vp, i32, dp, dp, dp]
     u32p, fp = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)
     L.lb_philox.argtypes = [ctypes.c_int64, u32p, u32p, u32p, fp, fp]
     L.lb2_create.argtypes = [i32, ctypes.POINTER(Params2), ctypes.c_uint64, ctypes.POINTER(vp)]

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -34,6 +35,37 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // longest step loop captured in one graph
 constexpr int64_t kMaxGraphSteps = 100000;
 
+}  // namespace
+
+// FP64 staging of lb_fields_static (the exported fields before their copy to
+// the host), one copy per GPU, held until the process ends.  In host code the
+// name is only a stand-in: the device address comes from hipGetSymbolAddress.
+constexpr size_t kStaticScratchDoubles = size_t(1) << 22;  // 32 MiB
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// This GPU's copy of the scratch array, looked up once per device with that
+// device current.
+int scratch_of(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return LB_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) return LB_EDEVICE;
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) return LB_EDEVICE;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) return LB_EDEVICE;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
 }  // namespace
 
 struct lb_sim {
@@ -1133,6 +1165,39 @@ int lb_fields(lb_sim *s, int replica, double *rho, double *j, double *f) {
     dev_release(s, df, sizeof(double) * Q * N);
     dev_release(s, dj, sizeof(double) * 3 * N);
     dev_release(s, drho, sizeof(double) * N);
+    if (rc) return rc;
+    return check_err(s);
+}
+
+int lb_fields_static(lb_sim *s, int replica, double *rho, double *j, double *f) {
+    if (!s || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    const RepDesc &d = s->hdesc[replica];
+    const size_t N = (size_t)d.N;
+    const size_t need = N * ((rho ? 1 : 0) + (j ? 3 : 0) + (f ? Q : 0));
+    if (need > kStaticScratchDoubles) return LB_EINVAL;
+    if (need == 0) return check_err(s);
+    double *base = nullptr;
+    int rc = scratch_of(s->device, &base);
+    if (rc) return rc;
+    double *drho = rho ? base : nullptr;
+    double *dj = j ? base + (rho ? N : 0) : nullptr;
+    double *df = f ? base + (rho ? N : 0) + (j ? 3 * N : 0) : nullptr;
+    const int cur = (int)(s->t & 1);
+    const unsigned nb = (unsigned)ceil_div(d.N, kBlock);
+    if (s->storage == LB_FP16)
+        hipLaunchKernelGGL(k_export<__half>, dim3(nb), dim3(kBlock), 0, s->stream, d,
+                           (const __half *)s->pop[cur] + Q * d.site_off, drho, dj, df);
+    else
+        hipLaunchKernelGGL(k_export<float>, dim3(nb), dim3(kBlock), 0, s->stream, d,
+                           (const float *)s->pop[cur] + Q * d.site_off, drho, dj, df);
+    if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
+    if (rc == LB_OK && rho && hipMemcpyAsync(rho, drho, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream))
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && j && hipMemcpyAsync(j, dj, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s->stream))
+        rc = LB_EDEVICE;
+    if (rc == LB_OK && f && hipMemcpyAsync(f, df, sizeof(double) * Q * N, hipMemcpyDeviceToHost, s->stream))
+        rc = LB_EDEVICE;
+    if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
     if (rc) return rc;
     return check_err(s);
 }
