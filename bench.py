@@ -24,6 +24,11 @@ Also reported on the same line:
   paper_model   short runs of the paper's own model (the GL pressure in the
                 equilibrium) on D3Q19 256^3 and D2Q9 256^2 and 2048^2, each
                 on its default plan with its roofline.
+  precision_variant
+                the 512^3 lattice with FP16 deviation storage beside FP32
+                storage, each on its default plan: whole steps with a
+                sample every 10, and the step kernel's roofline (76 and 152
+                algorithmic bytes per site update).
 
 --workload d3q19_256_eq | d2q9_256 | d2q9_2048 times one of those alone, with
 its own JSON line: the tuned plan (D3Q19), the roofline over its step
@@ -127,6 +132,8 @@ def main():
                     help="fixed launch plan kernel:tx:ty:tz:graph_steps (kernel split|fused|staged|rows)")
     ap.add_argument("--no-paper-model", action="store_true",
                     help="leave out the short runs of the paper's own model (D3Q19 and D2Q9)")
+    ap.add_argument("--no-precision-variant", action="store_true",
+                    help="leave out the 512^3 FP16-against-FP32 storage runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
@@ -240,9 +247,12 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(L, wl)
 
-    if not args.no_paper_model:
+    if not args.no_paper_model or not args.no_precision_variant:
         del sim
+    if not args.no_paper_model:
         result["paper_model"] = paper_model_summary(args, torch, lbf, workloads, stream)
+    if not args.no_precision_variant:
+        result["precision_variant"] = precision_variant_summary(torch, lbf, workloads, stream)
 
     print(json.dumps(result), flush=True)
 
@@ -406,6 +416,56 @@ def paper_model_summary(args, torch, lbf, workloads, stream):
                      "sample_every": r["config"]["sample_every"], "plan": r["config"]["plan"],
                      "kernel": rf["kernel"], "us_per_step": rf["us_per_step"], "achieved": rf["achieved"],
                      "frac": rf["frac"], "traffic": rf["traffic"], "valu_busy": rf["valu_busy"]}
+    return out
+
+
+def precision_variant_summary(torch, lbf, workloads, stream, steps=60, warmup=10, every=10):
+    """512^3 with FP16 deviation storage beside FP32 storage (same seed, the
+    default plan of each): whole steps with a sample every 10 timed around
+    the host clock, then the step kernel alone (graph replays, no samples)
+    with HIP events on its stream against the 8 TB/s HBM peak."""
+    wl = dict(workloads.WORKLOADS["d3q19_512_fp16"])
+    L = wl.pop("L")
+    wl.pop("steps")
+    wl.pop("storage")
+    N = L ** 3
+    out = {"workload": f"plain D3Q19 {L}^3 (d3q19_512_fp16)", "sites": N}
+    for storage in ("fp16", "fp32"):
+        log(f"[bench] precision variant: {L}^3 {storage}")
+        sim = lbf.Sim(L, workloads.SEED, storage=storage, sample_every=every, **wl)
+        plan = sim.plan()
+        sim.step(warmup)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mass = sim.moments()["mass"]
+        del sim
+        ksim = lbf.Sim(L, workloads.SEED, storage=storage, **wl)
+        ksim.set_plan(KERNEL_NAMES[plan["kernel"]], (plan["tile_x"], plan["tile_y"], plan["tile_z"]), 20)
+        ksim.step(20)
+        ksim.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        nk = 100
+        e0.record(stream)
+        ksim.step(nk)
+        e1.record(stream)
+        e1.synchronize()
+        ksim.sync()
+        del ksim
+        us = e0.elapsed_time(e1) / nk * 1e3
+        achieved = BYTES_PER_SITE[storage] * N / (us * 1e-6) / 1e9
+        out[storage] = {"value": round(N * steps / dt / 1e6, 1), "unit": "MLUPS", "steps": steps,
+                        "ms_per_step": round(dt / steps * 1e3, 3), "sample_every": every, "plan": plan,
+                        "kernel": "k_fused_staged" if plan["kernel"] == 3 else KERNEL_NAMES[plan["kernel"]],
+                        "us_per_launch": round(us, 1), "bytes_per_site": BYTES_PER_SITE[storage],
+                        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit_roofline": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "mass": mass}
+        log(f"[bench] {storage}: {out[storage]['value']} MLUPS whole step, kernel {us:.0f} us, "
+            f"{out[storage]['frac']:.3f} of 8 TB/s")
     return out
 
 
