@@ -395,9 +395,62 @@ def bench_paper_model(args, wl, torch, lbf, workloads, stream):
                      "us_per_step": round(ms_per_step * 1e3, 2), "device_copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
     }
+    if model == "d2q9" and L <= 512 and not args.no_batched:
+        result["batched"] = d2q9_batched(lbf, workloads, torch, stream, L, wl, every)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline_paper_model(model, L, wl)
     return result
+
+
+def d2q9_batched(lbf, workloads, torch, stream, L, wl, every, reps=64, steps=200):
+    """The paper's realizations side by side: 64 replicas of the L x L D2Q9
+    lattice in one handle (one launch per step over every replica) against
+    one replica in its own handle, same parameters and sample spacing; the
+    first replica's state equals the lone handle's bit for bit.  Beside it
+    the batch's step kernel alone (no samples) against the HBM roofline."""
+    import numpy as np
+    prms = [dict(wl, sample_every=every) for _ in range(reps)]
+    seeds = [workloads.SEED + r for r in range(reps)]
+    log(f"[bench] d2q9 batch: {reps} replicas of {L}^2")
+
+    def timed(sim, n):
+        sim.step(10)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(n)
+        sim.sync()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    bat = lbf.Sim2D.batch(L, seeds, prms)
+    t_bat = timed(bat, steps)
+    one = lbf.Sim2D(L, seeds[0], **prms[0])
+    t_one = timed(one, steps)
+    same = bool(np.array_equal(bat.fields(f=True, replica=0)["f"], one.fields(f=True)["f"]))
+    del bat, one
+    k = lbf.Sim2D.batch(L, seeds, [dict(p, sample_every=0) for p in prms])
+    k.step(20)
+    k.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    k.step(100)
+    e1.record(stream)
+    e1.synchronize()
+    k.sync()
+    del k
+    us = e0.elapsed_time(e1) / 100 * 1e3
+    sites = reps * L * L
+    achieved = 72.0 * sites / (us * 1e-6) / 1e9
+    out = {"replicas": reps, "L": L, "sites": sites, "steps": steps, "sample_every": every,
+           "batched_mlups": round(sites * steps / t_bat / 1e6, 1),
+           "one_handle_mlups": round(L * L * steps / t_one / 1e6, 1),
+           "speedup": round((sites / t_bat) / (L * L / t_one), 2), "identical_results": same,
+           "kernel": "k2_step_tiled", "us_per_step": round(us, 2), "achieved": round(achieved, 1),
+           "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    log(f"[bench] d2q9 batch {out['batched_mlups']} MLUPS vs one handle {out['one_handle_mlups']} MLUPS: "
+        f"x{out['speedup']}; kernel {us:.1f} us per step ({out['frac']:.3f} of 8 TB/s)")
+    return out
 
 
 def paper_model_summary(args, torch, lbf, workloads, stream):
@@ -409,13 +462,15 @@ def paper_model_summary(args, torch, lbf, workloads, stream):
     for name in ("d3q19_256_eq", "d2q9_256", "d2q9_2048"):
         sub = argparse.Namespace(**dict(vars(args), workload=name, steps=200, warmup=20, no_tune=True,
                                         no_cpu_baseline=True, kernel_only=False, plan=None, calibrate_copy=False,
-                                        storage="fp32"))
+                                        storage="fp32", no_batched=name != "d2q9_256"))
         r = bench_paper_model(sub, dict(workloads.WORKLOADS[name]), torch, lbf, workloads, stream)
         rf = r["roofline"]
         out[name] = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"],
                      "sample_every": r["config"]["sample_every"], "plan": r["config"]["plan"],
                      "kernel": rf["kernel"], "us_per_step": rf["us_per_step"], "achieved": rf["achieved"],
                      "frac": rf["frac"], "traffic": rf["traffic"], "valu_busy": rf["valu_busy"]}
+        if "batched" in r:
+            out[name]["batched"] = r["batched"]
     return out
 
 

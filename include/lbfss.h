@@ -432,25 +432,33 @@ typedef struct {
 /* 4 <= L <= 2048.  The initial state is rho = rho_c + init_sigma g (Philox
  * domain 1, call 0, first normal), u = 0, the equilibrium of that density. */
 int lb2_create(int L, const lb2_params *p, uint64_t seed, lb2_sim **out);
-int lb2_step(lb2_sim *s, int64_t n);   /* asynchronous */
+
+/* n >= 1 replicas of one lattice edge L in one handle, replica r with
+ * parameters p[r] and seed seeds[r] (the paper averages over a few hundred
+ * realizations, Sec. III B): each step is one launch over every replica's
+ * tiles, and each replica evolves bit for bit as it does alone under
+ * lb2_create.  All sample_every equal; n L^2 <= 2^31; else LB_EINVAL. */
+int lb2_create_batch(int n, int L, const lb2_params *p, const uint64_t *seeds, lb2_sim **out);
+int lb2_step(lb2_sim *s, int64_t n);   /* asynchronous; every replica */
 int lb2_sync(lb2_sim *s);
 /* Order all later device work of the handle on hip_stream (a hipStream_t;
  * NULL selects the handle's own stream), as lb_set_stream.  Synchronises
  * the previous stream; the caller keeps ownership of hip_stream, which must
  * outlive its use by the handle. */
 int lb2_set_stream(lb2_sim *s, void *hip_stream);
-/* rho (L^2), j ([2][L^2]) and f ([9][L^2]) of the current state; any may be
- * NULL; caller-owned FP64 buffers; synchronises. */
-int lb2_fields(lb2_sim *s, double *rho, double *j, double *f);
-int lb2_set_populations(lb2_sim *s, const double *f);
-/* Accumulated spectra over the samples, each [ky][kx] (L^2 doubles, k index
+/* rho (L^2), j ([2][L^2]) and f ([9][L^2]) of the current state of one
+ * replica (0 for lb2_create); any may be NULL; caller-owned FP64 buffers;
+ * synchronises.  LB_EINVAL for a bad replica index. */
+int lb2_fields(lb2_sim *s, int replica, double *rho, double *j, double *f);
+int lb2_set_populations(lb2_sim *s, int replica, const double *f);
+/* Accumulated spectra of one replica over the samples, each [ky][kx] (L^2 doubles, k index
  * m in 0..L-1, wave number 2 pi m / L): S = <|drho_k|^2>/N, J_x, J_y =
  * <|j_a,k|^2>/N, J_par, J_perp = the same for the projections of j_k on the
  * direction of k (folded into (-L/2, L/2]) and across it (0 at k = 0):
  * sums over samples, n_samples of them.  Any array may be NULL. */
-int lb2_spectra(lb2_sim *s, int64_t *n_samples, double *S, double *Jx, double *Jy, double *Jpar,
+int lb2_spectra(lb2_sim *s, int replica, int64_t *n_samples, double *S, double *Jx, double *Jy, double *Jpar,
                 double *Jperp);
-int lb2_reset_spectra(lb2_sim *s);
+int lb2_reset_spectra(lb2_sim *s);  /* every replica */
 void lb2_destroy(lb2_sim *s);
 
 #ifdef __cplusplus

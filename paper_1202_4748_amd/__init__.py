@@ -28,7 +28,7 @@ EXPORTS = ("lb_create", "lb_create_batch", "lb_step", "lb_sync", "lb_moments", "
            "lb_set_plan", "lb_get_plan", "lb_tune", "lb_info", "lb_destroy", "lb_strerror",
            "lb_histogram", "lb_hist_estimates", "lb_sk3_shells", "lb_sk3", "lb_oz_fit",
            "lb_set_step", "lb_philox", "lb_fields_static",
-           "lb2_create", "lb2_step", "lb2_sync", "lb2_set_stream", "lb2_fields", "lb2_set_populations",
+           "lb2_create", "lb2_create_batch", "lb2_step", "lb2_sync", "lb2_set_stream", "lb2_fields", "lb2_set_populations",
            "lb2_spectra", "lb2_reset_spectra", "lb2_destroy")
 
 
@@ -142,12 +142,14 @@ def lib():
     u32p, fp = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)
     L.lb_philox.argtypes = [ctypes.c_int64, u32p, u32p, u32p, fp, fp]
     L.lb2_create.argtypes = [i32, ctypes.POINTER(Params2), ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.lb2_create_batch.argtypes = [i32, i32, ctypes.POINTER(Params2), ctypes.POINTER(ctypes.c_uint64),
+                                   ctypes.POINTER(vp)]
     L.lb2_step.argtypes = [vp, ctypes.c_int64]
     L.lb2_sync.argtypes = [vp]
     L.lb2_set_stream.argtypes = [vp, vp]
-    L.lb2_fields.argtypes = [vp, dp, dp, dp]
-    L.lb2_set_populations.argtypes = [vp, dp]
-    L.lb2_spectra.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), dp, dp, dp, dp, dp]
+    L.lb2_fields.argtypes = [vp, i32, dp, dp, dp]
+    L.lb2_set_populations.argtypes = [vp, i32, dp]
+    L.lb2_spectra.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), dp, dp, dp, dp, dp]
     L.lb2_reset_spectra.argtypes = [vp]
     L.lb2_destroy.argtypes = [vp]
     L.lb2_destroy.restype = None
@@ -406,22 +408,41 @@ def philox(ctr, key):
 class Sim2D:
     """The paper's own D2Q9 model (Sec. III A) on an L x L lattice: the
     Ginzburg-Landau pressure in a modified equilibrium, local-sound-speed
-    noise covariance (see the lb2_* section of include/lbfss.h)."""
+    noise covariance (see the lb2_* section of include/lbfss.h).
+    ``Sim2D.batch(L, seeds, params_list)`` holds many replicas of one L."""
 
-    def __init__(self, L, seed=0, a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, init_sigma=1e-3,
-                 sample_every=0):
+    def __init__(self, L=None, seed=0, a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, init_sigma=1e-3,
+                 sample_every=0, _handle=None, _n=1):
         L_ = lib()
         _use_torch()
         self.L = int(L)
-        p = Params2(a, b, kappa, rho_c, kT, tau, init_sigma, int(sample_every), 0)
-        h = ctypes.c_void_p()
-        _check(L_.lb2_create(self.L, ctypes.byref(p), ctypes.c_uint64(seed), ctypes.byref(h)), "lb2_create")
-        self._h = h
+        self.n = int(_n)
+        if _handle is not None:
+            self._h = _handle
+        else:
+            p = Params2(a, b, kappa, rho_c, kT, tau, init_sigma, int(sample_every), 0)
+            h = ctypes.c_void_p()
+            _check(L_.lb2_create(self.L, ctypes.byref(p), ctypes.c_uint64(seed), ctypes.byref(h)), "lb2_create")
+            self._h = h
         if _use_torch():
             import torch
             cs = torch.cuda.current_stream().cuda_stream
             if cs:  # as Sim: torch's current stream unless it is the legacy default one
                 _check(L_.lb2_set_stream(self._h, ctypes.c_void_p(cs)), "lb2_set_stream")
+
+    @classmethod
+    def batch(cls, L, seeds, params_list):
+        L_ = lib()
+        _use_torch()
+        n = len(seeds)
+        keys = ("a", "b", "kappa", "rho_c", "kT", "tau", "init_sigma", "sample_every")
+        dflt = dict(a=0.0, b=0.0, kappa=0.0, rho_c=1.0, kT=0.0, tau=1.0, init_sigma=1e-3, sample_every=0)
+        arrP = (Params2 * n)(*[Params2(*[dict(dflt, **p)[k] for k in keys[:7]],
+                                       int(dict(dflt, **p)["sample_every"]), 0) for p in params_list])
+        arrS = (ctypes.c_uint64 * n)(*[int(s) for s in seeds])
+        h = ctypes.c_void_p()
+        _check(L_.lb2_create_batch(n, int(L), arrP, arrS, ctypes.byref(h)), "lb2_create_batch")
+        return cls(L, _handle=h, _n=n)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -437,27 +458,27 @@ class Sim2D:
     def sync(self):
         _check(lib().lb2_sync(self._h), "lb2_sync")
 
-    def fields(self, f=False):
+    def fields(self, f=False, replica=0):
         N = self.L * self.L
         rho, j = np.zeros(N), np.zeros(2 * N)
         ff = np.zeros(9 * N) if f else None
-        _check(lib().lb2_fields(self._h, _dp(rho), _dp(j), _dp(ff)), "lb2_fields")
+        _check(lib().lb2_fields(self._h, int(replica), _dp(rho), _dp(j), _dp(ff)), "lb2_fields")
         out = {"rho": rho, "j": j.reshape(2, N)}
         if f:
             out["f"] = ff.reshape(9, N)
         return out
 
-    def set_populations(self, f):
+    def set_populations(self, f, replica=0):
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
-        _check(lib().lb2_set_populations(self._h, _dp(f)), "lb2_set_populations")
+        _check(lib().lb2_set_populations(self._h, int(replica), _dp(f)), "lb2_set_populations")
 
-    def spectra(self):
+    def spectra(self, replica=0):
         """Sums over samples of the spectra, each [ky, kx]: S, Jx, Jy, Jpar,
         Jperp; and n_samples."""
         N = self.L * self.L
         arr = [np.zeros(N) for _ in range(5)]
         n = ctypes.c_int64()
-        _check(lib().lb2_spectra(self._h, ctypes.byref(n), *[_dp(a) for a in arr]), "lb2_spectra")
+        _check(lib().lb2_spectra(self._h, int(replica), ctypes.byref(n), *[_dp(a) for a in arr]), "lb2_spectra")
         out = {k: a.reshape(self.L, self.L) for k, a in zip(("S", "Jx", "Jy", "Jpar", "Jperp"), arr)}
         out["n_samples"] = n.value
         return out

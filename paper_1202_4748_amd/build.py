@@ -1,5 +1,6 @@
 """Compile the HIP library ``liblbfss.so`` for gfx950 (in-tree, under _build/)."""
 import os
+import re
 import subprocess
 import sys
 
@@ -24,14 +25,53 @@ HIPCC_FLAGS = [
 ]
 
 
+# kernels whose hand-written s_waitcnt counts every vector-memory operation a
+# wave issues: scratch (register spills) would add uncounted ones
+COUNTED_WAIT_KERNELS = ("k_fused_staged", "k_meq_staged")
+
+
+def resource_usage(remarks: str):
+    """{mangled kernel name: {field: value}} from the compiler's
+    kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+([A-Za-z][A-Za-z /\[\]]*?):\s+(\S+) \[-Rpass-analysis", line)
+        if m and cur is not None:
+            cur[m.group(1).strip()] = m.group(2)
+    return out
+
+
+def check_counted_waits(usage):
+    bad = [(k, v) for k, v in usage.items() if any(n in k for n in COUNTED_WAIT_KERNELS)
+           and (v.get("ScratchSize [bytes/lane]", "0") != "0" or v.get("VGPRs Spill", "0") != "0")]
+    if bad:
+        raise RuntimeError("kernels with counted waits use scratch memory: " +
+                           ", ".join(f"{k} ({v.get('ScratchSize [bytes/lane]')} B/lane)" for k, v in bad))
+    n = sum(1 for k in usage if any(c in k for c in COUNTED_WAIT_KERNELS))
+    if n == 0:
+        raise RuntimeError("no resource-usage remarks for the staged kernels")
+    return n
+
+
 def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-Rpass-analysis=kernel-resource-usage", "-I",
+           os.path.join(ROOT, "include"), "-o", tmp, SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stderr)
+        raise subprocess.CalledProcessError(r.returncode, cmd)
+    n = check_counted_waits(resource_usage(r.stderr))
+    if verbose:
+        print(f"{n} staged kernel instances without scratch memory", flush=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -1476,16 +1476,19 @@ const char *lb_strerror(int code) {
 // ---------------------------------------------------------------------------
 struct lb2_sim {
     int L = 0;
-    lb2_params P{};
-    D2Desc D{};
+    int nrep = 0;
+    int sample_every = 0;
+    std::vector<lb2_params> P;
+    std::vector<D2Desc> D;
+    D2Desc *d_desc = nullptr;
     hipStream_t stream = nullptr, own_stream = nullptr;
     Allocator alloc;
     std::vector<void *> blocks;
-    float *pop[2] = {nullptr, nullptr};
+    float *pop[2] = {nullptr, nullptr};  // [replica][9][L^2]
     float *d_drho = nullptr;
     int *d_err = nullptr;
-    double *d_twid = nullptr, *d_snap = nullptr, *d_acc = nullptr;
-    double2 *d_X = nullptr;
+    double *d_twid = nullptr, *d_snap = nullptr, *d_acc = nullptr;  // per replica [3][L^2], [5][L^2]
+    double2 *d_X = nullptr;                                         // per replica [3][L^2]
     int64_t t = 0, n_samples = 0;
 };
 
@@ -1496,6 +1499,11 @@ void *dev_alloc2(lb2_sim *s, size_t bytes) {
     else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
     if (p) s->blocks.push_back(p);
     return p;
+}
+
+bool lb2_params_ok(const lb2_params *p) {
+    return p && p->tau > 0.5 && p->kT >= 0 && p->kappa >= 0 && p->b >= 0 && p->rho_c > 0 && p->init_sigma >= 0 &&
+           std::isfinite(p->a) && p->sample_every >= 0 && p->reserved == 0;
 }
 }  // namespace
 
@@ -1510,47 +1518,55 @@ void lb2_destroy(lb2_sim *s) {
     delete s;
 }
 
-int lb2_create(int L, const lb2_params *p, uint64_t seed, lb2_sim **out) {
-    if (!out || !p) return LB_EINVAL;
+int lb2_create_batch(int n, int L, const lb2_params *p, const uint64_t *seeds, lb2_sim **out) {
+    if (!out || !p || !seeds || n < 1) return LB_EINVAL;
     *out = nullptr;
-    if (L < 4 || L > 2048 || !(p->tau > 0.5) || !(p->kT >= 0) || !(p->kappa >= 0) || !(p->b >= 0) ||
-        !(p->rho_c > 0) || !(p->init_sigma >= 0) || !std::isfinite(p->a) || p->sample_every < 0 || p->reserved != 0)
-        return LB_EINVAL;
+    if (L < 4 || L > 2048) return LB_EINVAL;
+    for (int r = 0; r < n; ++r)
+        if (!lb2_params_ok(&p[r]) || p[r].sample_every != p[0].sample_every) return LB_EINVAL;
+    const int64_t N = (int64_t)L * L;
+    if ((int64_t)n * N > (int64_t)1 << 31) return LB_EINVAL;  // site and tile indices stay within 32 bits
     lb2_sim *s = new (std::nothrow) lb2_sim();
     if (!s) return LB_ENOMEM;
     s->alloc = g_alloc;
     s->L = L;
-    s->P = *p;
+    s->nrep = n;
+    s->sample_every = p[0].sample_every;
     auto fail = [&](int code) {
         lb2_destroy(s);
         return code;
     };
     if (hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking) != hipSuccess) return fail(LB_EDEVICE);
     s->stream = s->own_stream;
-    const double gam = 1.0 - 1.0 / p->tau;
-    s->D.L = L;
-    s->D.a = (float)p->a;
-    s->D.b = (float)p->b;
-    s->D.kappa = (float)p->kappa;
-    s->D.rho_c = (float)p->rho_c;
-    s->D.gamma = (float)gam;
-    s->D.nu = (float)((p->tau - 0.5) / 3.0);
-    s->D.noise_amp = (float)std::sqrt(3.0 * p->kT * (1.0 - gam * gam));
-    s->D.key0 = (uint32_t)seed;
-    s->D.key1 = (uint32_t)(seed >> 32);
-    const int64_t N = (int64_t)L * L;
+    for (int r = 0; r < n; ++r) {
+        const double gam = 1.0 - 1.0 / p[r].tau;
+        D2Desc D{};
+        D.L = L;
+        D.a = (float)p[r].a;
+        D.b = (float)p[r].b;
+        D.kappa = (float)p[r].kappa;
+        D.rho_c = (float)p[r].rho_c;
+        D.gamma = (float)gam;
+        D.nu = (float)((p[r].tau - 0.5) / 3.0);
+        D.noise_amp = (float)std::sqrt(3.0 * p[r].kT * (1.0 - gam * gam));
+        D.key0 = (uint32_t)seeds[r];
+        D.key1 = (uint32_t)(seeds[r] >> 32);
+        s->D.push_back(D);
+        s->P.push_back(p[r]);
+    }
     for (int b = 0; b < 2; ++b)
-        if (!(s->pop[b] = (float *)dev_alloc2(s, sizeof(float) * Q2 * N))) return fail(LB_ENOMEM);
+        if (!(s->pop[b] = (float *)dev_alloc2(s, sizeof(float) * Q2 * N * n))) return fail(LB_ENOMEM);
     s->d_drho = (float *)dev_alloc2(s, sizeof(float) * N);
     s->d_err = (int *)dev_alloc2(s, sizeof(int));
     s->d_twid = (double *)dev_alloc2(s, sizeof(double) * 2 * L);
-    if (!s->d_drho || !s->d_err || !s->d_twid) return fail(LB_ENOMEM);
-    if (p->sample_every > 0) {
-        s->d_snap = (double *)dev_alloc2(s, sizeof(double) * 3 * N);
-        s->d_X = (double2 *)dev_alloc2(s, sizeof(double2) * 3 * N);
-        s->d_acc = (double *)dev_alloc2(s, sizeof(double) * 5 * N);
+    s->d_desc = (D2Desc *)dev_alloc2(s, sizeof(D2Desc) * n);
+    if (!s->d_drho || !s->d_err || !s->d_twid || !s->d_desc) return fail(LB_ENOMEM);
+    if (s->sample_every > 0) {
+        s->d_snap = (double *)dev_alloc2(s, sizeof(double) * 3 * N * n);
+        s->d_X = (double2 *)dev_alloc2(s, sizeof(double2) * 3 * N * n);
+        s->d_acc = (double *)dev_alloc2(s, sizeof(double) * 5 * N * n);
         if (!s->d_snap || !s->d_X || !s->d_acc) return fail(LB_ENOMEM);
-        if (hipMemsetAsync(s->d_acc, 0, sizeof(double) * 5 * N, s->stream) != hipSuccess) return fail(LB_EDEVICE);
+        if (hipMemsetAsync(s->d_acc, 0, sizeof(double) * 5 * N * n, s->stream) != hipSuccess) return fail(LB_EDEVICE);
     }
     std::vector<double> tw(2 * L);
     for (int k = 0; k < L; ++k) {
@@ -1558,15 +1574,23 @@ int lb2_create(int L, const lb2_params *p, uint64_t seed, lb2_sim **out) {
         tw[L + k] = std::sin(2.0 * M_PI * k / L);
     }
     if (hipMemcpyAsync(s->d_twid, tw.data(), sizeof(double) * 2 * L, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_desc, s->D.data(), sizeof(D2Desc) * n, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemsetAsync(s->d_err, 0, sizeof(int), s->stream) != hipSuccess)
         return fail(LB_EDEVICE);
     const unsigned nb = (unsigned)ceil_div(N, kBlock);
-    hipLaunchKernelGGL(k2_init_density, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (float)p->init_sigma, s->d_drho);
-    hipLaunchKernelGGL(k2_init_populations, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->d_drho,
-                       s->pop[0]);
+    for (int r = 0; r < n; ++r) {
+        hipLaunchKernelGGL(k2_init_density, dim3(nb), dim3(kBlock), 0, s->stream, s->D[r], (float)p[r].init_sigma,
+                           s->d_drho);
+        hipLaunchKernelGGL(k2_init_populations, dim3(nb), dim3(kBlock), 0, s->stream, s->D[r],
+                           (const float *)s->d_drho, s->pop[0] + (int64_t)r * Q2 * N);
+    }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) return fail(LB_EDEVICE);
     *out = s;
     return LB_OK;
+}
+
+int lb2_create(int L, const lb2_params *p, uint64_t seed, lb2_sim **out) {
+    return lb2_create_batch(1, L, p, &seed, out);
 }
 
 namespace {
@@ -1583,30 +1607,45 @@ int lb2_step(lb2_sim *s, int64_t n) {
     if (!s || n < 0) return LB_EINVAL;
     const int64_t N = (int64_t)s->L * s->L;
     const unsigned nb = (unsigned)ceil_div(N, kBlock);
-    const unsigned tiles = (unsigned)(ceil_div(s->L, K2TX) * ceil_div(s->L, K2TY));
+    const int tiles = (int)(ceil_div(s->L, K2TX) * ceil_div(s->L, K2TY));
+    const unsigned R = (unsigned)s->nrep;
     for (int64_t k = 0; k < n; ++k) {
         const int cur = (int)(s->t & 1);
-        hipLaunchKernelGGL(k2_step_tiled, dim3(tiles), dim3(K2TX * K2TY), 0, s->stream, s->D,
-                           (const float *)s->pop[cur], s->pop[cur ^ 1], (uint64_t)s->t, s->d_err);
+        hipLaunchKernelGGL(k2_step_tiled, dim3((unsigned)tiles * R), dim3(K2TX * K2TY), 0, s->stream,
+                           (const D2Desc *)s->d_desc, tiles, (const float *)s->pop[cur], s->pop[cur ^ 1], (uint64_t)s->t,
+                           s->d_err);
         s->t += 1;
-        if (s->P.sample_every > 0 && s->t % s->P.sample_every == 0) {
-            hipLaunchKernelGGL(k2_snap, dim3(nb), dim3(kBlock), 0, s->stream, s->D, (const float *)s->pop[cur ^ 1],
-                               s->d_snap);
+        if (s->sample_every > 0 && s->t % s->sample_every == 0) {
             const unsigned lines = (unsigned)(3 * s->L);
-            if ((s->L & (s->L - 1)) == 0) {  // power of two: FFTs
-                int logL = 0;
-                while ((1 << logL) < s->L) ++logL;
-                hipLaunchKernelGGL(k2_fft_rows, dim3(lines), dim3(kBlock), 0, s->stream, s->L, logL,
+            const bool pow2 = (s->L & (s->L - 1)) == 0;
+            int logL = 0;
+            while ((1 << logL) < s->L) ++logL;
+            if (pow2 && s->L <= kK2LinesMaxL) {  // three lines per workgroup, no snapshot array
+                const bool small = s->L <= 256;  // 12 KB of LDS lines instead of 48 KB
+                hipLaunchKernelGGL(small ? k2_snap_fft_rows<256> : k2_snap_fft_rows<kK2LinesMaxL>,
+                                   dim3((unsigned)s->L, R), dim3(kBlock), 0, s->stream, s->L, logL,
+                                   (const float *)s->pop[cur ^ 1], (const double *)s->d_twid, s->d_X);
+                hipLaunchKernelGGL(small ? k2_fft_cols3<256> : k2_fft_cols3<kK2LinesMaxL>, dim3((unsigned)s->L, R),
+                                   dim3(kBlock), 0, s->stream, s->L, logL, s->d_X, (const double *)s->d_twid);
+                hipLaunchKernelGGL(k2_spec_acc, dim3(nb, R), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
+                                   s->d_acc);
+                s->n_samples += 1;
+                continue;
+            }
+            hipLaunchKernelGGL(k2_snap, dim3(nb, R), dim3(kBlock), 0, s->stream, s->L, (const float *)s->pop[cur ^ 1],
+                               s->d_snap);
+            if (pow2) {  // FFTs
+                hipLaunchKernelGGL(k2_fft_rows, dim3(lines, R), dim3(kBlock), 0, s->stream, s->L, logL,
                                    (const double *)s->d_snap, (const double *)s->d_twid, s->d_X);
-                hipLaunchKernelGGL(k2_fft_cols, dim3(lines), dim3(kBlock), 0, s->stream, s->L, logL, s->d_X,
+                hipLaunchKernelGGL(k2_fft_cols, dim3(lines, R), dim3(kBlock), 0, s->stream, s->L, logL, s->d_X,
                                    (const double *)s->d_twid);
-                hipLaunchKernelGGL(k2_spec_acc, dim3(nb), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
+                hipLaunchKernelGGL(k2_spec_acc, dim3(nb, R), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
                                    s->d_acc);
             } else {
-                hipLaunchKernelGGL(k2_dft_rows, dim3(lines), dim3(kBlock), 0, s->stream, s->L,
+                hipLaunchKernelGGL(k2_dft_rows, dim3(lines, R), dim3(kBlock), 0, s->stream, s->L,
                                    (const double *)s->d_snap, (const double *)s->d_twid, s->d_X);
-                hipLaunchKernelGGL(k2_dft_cols, dim3(nb), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
-                                   (const double *)s->d_twid, s->d_acc);
+                hipLaunchKernelGGL(k2_dft_cols, dim3(nb, R), dim3(kBlock), 0, s->stream, s->L,
+                                   (const double2 *)s->d_X, (const double *)s->d_twid, s->d_acc);
             }
             s->n_samples += 1;
         }
@@ -1626,8 +1665,8 @@ int lb2_set_stream(lb2_sim *s, void *hip_stream) {
     return LB_OK;
 }
 
-int lb2_fields(lb2_sim *s, double *rho, double *j, double *f) {
-    if (!s) return LB_EINVAL;
+int lb2_fields(lb2_sim *s, int replica, double *rho, double *j, double *f) {
+    if (!s || replica < 0 || replica >= s->nrep) return LB_EINVAL;
     const int64_t N = (int64_t)s->L * s->L;
     const size_t need = (size_t)(rho ? N : 0) + (j ? 2 * N : 0) + (f ? Q2 * N : 0);
     if (need == 0) return check2(s);
@@ -1637,8 +1676,8 @@ int lb2_fields(lb2_sim *s, double *rho, double *j, double *f) {
     double *dj = j ? buf + (rho ? N : 0) : nullptr;
     double *df = f ? buf + (rho ? N : 0) + (j ? 2 * N : 0) : nullptr;
     int rc = LB_OK;
-    hipLaunchKernelGGL(k2_export, dim3((unsigned)ceil_div(N, kBlock)), dim3(kBlock), 0, s->stream, s->D,
-                       (const float *)s->pop[s->t & 1], dr, dj, df);
+    hipLaunchKernelGGL(k2_export, dim3((unsigned)ceil_div(N, kBlock)), dim3(kBlock), 0, s->stream, s->D[replica],
+                       (const float *)s->pop[s->t & 1] + (int64_t)replica * Q2 * N, dr, dj, df);
     if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
     if (rc == LB_OK && rho && hipMemcpyAsync(rho, dr, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream)) rc = LB_EDEVICE;
     if (rc == LB_OK && j && hipMemcpyAsync(j, dj, sizeof(double) * 2 * N, hipMemcpyDeviceToHost, s->stream)) rc = LB_EDEVICE;
@@ -1650,16 +1689,16 @@ int lb2_fields(lb2_sim *s, double *rho, double *j, double *f) {
     return rc ? rc : check2(s);
 }
 
-int lb2_set_populations(lb2_sim *s, const double *f) {
-    if (!s || !f) return LB_EINVAL;
+int lb2_set_populations(lb2_sim *s, int replica, const double *f) {
+    if (!s || !f || replica < 0 || replica >= s->nrep) return LB_EINVAL;
     const int64_t N = (int64_t)s->L * s->L;
     double *df = (double *)dev_alloc2(s, sizeof(double) * Q2 * N);
     if (!df) return LB_ENOMEM;
     int rc = LB_OK;
     if (hipMemcpyAsync(df, f, sizeof(double) * Q2 * N, hipMemcpyHostToDevice, s->stream) != hipSuccess) rc = LB_EDEVICE;
     if (rc == LB_OK) {
-        hipLaunchKernelGGL(k2_import, dim3((unsigned)ceil_div(N, kBlock)), dim3(kBlock), 0, s->stream, s->D,
-                           (const double *)df, s->pop[s->t & 1]);
+        hipLaunchKernelGGL(k2_import, dim3((unsigned)ceil_div(N, kBlock)), dim3(kBlock), 0, s->stream, s->D[replica],
+                           (const double *)df, s->pop[s->t & 1] + (int64_t)replica * Q2 * N);
         if (hipGetLastError() != hipSuccess) rc = LB_EDEVICE;
     }
     if (hipStreamSynchronize(s->stream) != hipSuccess && rc == LB_OK) rc = LB_EDEVICE;
@@ -1669,14 +1708,16 @@ int lb2_set_populations(lb2_sim *s, const double *f) {
     return rc ? rc : check2(s);
 }
 
-int lb2_spectra(lb2_sim *s, int64_t *n_samples, double *S, double *Jx, double *Jy, double *Jpar, double *Jperp) {
-    if (!s || !n_samples) return LB_EINVAL;
-    if (s->P.sample_every <= 0) return LB_ESTATE;
+int lb2_spectra(lb2_sim *s, int replica, int64_t *n_samples, double *S, double *Jx, double *Jy, double *Jpar,
+                double *Jperp) {
+    if (!s || !n_samples || replica < 0 || replica >= s->nrep) return LB_EINVAL;
+    if (s->sample_every <= 0) return LB_ESTATE;
     const int64_t N = (int64_t)s->L * s->L;
+    const double *acc = s->d_acc + (int64_t)replica * 5 * N;
     double *dst[5] = {S, Jx, Jy, Jpar, Jperp};
     for (int c = 0; c < 5; ++c)
-        if (dst[c] && hipMemcpyAsync(dst[c], s->d_acc + c * N, sizeof(double) * N, hipMemcpyDeviceToHost,
-                                     s->stream) != hipSuccess)
+        if (dst[c] && hipMemcpyAsync(dst[c], acc + c * N, sizeof(double) * N, hipMemcpyDeviceToHost, s->stream) !=
+                          hipSuccess)
             return LB_EDEVICE;
     if (hipStreamSynchronize(s->stream) != hipSuccess) return LB_EDEVICE;
     *n_samples = s->n_samples;
@@ -1685,9 +1726,9 @@ int lb2_spectra(lb2_sim *s, int64_t *n_samples, double *S, double *Jx, double *J
 
 int lb2_reset_spectra(lb2_sim *s) {
     if (!s) return LB_EINVAL;
-    if (s->P.sample_every <= 0) return LB_ESTATE;
+    if (s->sample_every <= 0) return LB_ESTATE;
     const int64_t N = (int64_t)s->L * s->L;
-    if (hipMemsetAsync(s->d_acc, 0, sizeof(double) * 5 * N, s->stream) != hipSuccess) return LB_EDEVICE;
+    if (hipMemsetAsync(s->d_acc, 0, sizeof(double) * 5 * N * s->nrep, s->stream) != hipSuccess) return LB_EDEVICE;
     s->n_samples = 0;
     return LB_OK;
 }

@@ -205,17 +205,24 @@ __device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2],
 // Tiles are numbered x fastest and dealt to the XCDs in contiguous runs
 // (xcd_tile), so the halo pulls of a tile find its neighbours' rows in the
 // same L2.  64 x 4 tiles: 3% faster than 32 x 8 at 2048^2, 16 x 16 12% slower.
+// A batch of replicas (one L, own parameters and seeds) is one launch: the
+// tiles of replica r follow those of replica r - 1, each replica's
+// populations a [9][L^2] block after the previous one's.
 constexpr int K2TX = 64, K2TY = 4;
 __global__ void __launch_bounds__(K2TX * K2TY)
-k2_step_tiled(D2Desc D, const float *__restrict__ pop, float *__restrict__ pop_out, uint64_t t,
-              int *__restrict__ err) {
+k2_step_tiled(const D2Desc *__restrict__ descs, int tiles_per_rep, const float *__restrict__ pop_all,
+              float *__restrict__ pop_out_all, uint64_t t, int *__restrict__ err) {
     constexpr int EX = K2TX + 2;
     static_assert(2 * (K2TX + 2) + 2 * K2TY <= K2TX * K2TY, "one halo site per thread");
     __shared__ float s_rho[EX * (K2TY + 2)];
+    const int gtile = xcd_tile(blockIdx.x, gridDim.x);
+    const int rep = gtile / tiles_per_rep, tile = gtile - rep * tiles_per_rep;
+    const D2Desc D = descs[rep];
     const int L = D.L;
     const int64_t N = (int64_t)L * L;
+    const float *pop = pop_all + (int64_t)rep * Q2 * N;
+    float *pop_out = pop_out_all + (int64_t)rep * Q2 * N;
     const int ntx = (L + K2TX - 1) / K2TX;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int x0 = (tile % ntx) * K2TX, y0 = (tile / ntx) * K2TY;
     const int nx = min(K2TX, L - x0), ny = min(K2TY, L - y0);
     const int tid = threadIdx.x, ix = tid % K2TX, iy = tid / K2TX;
@@ -343,10 +350,12 @@ k2_import(D2Desc D, const double *__restrict__ f, float *__restrict__ pop) {
 }
 
 // Sampling: density deviation and momentum of the state, FP64 [3][L^2].
+// (The sampling kernels take replica blockIdx.y of a batch.)
 __global__ void __launch_bounds__(kBlock)
-k2_snap(D2Desc D, const float *__restrict__ pop, double *__restrict__ out) {
-    const int L = D.L;
+k2_snap(int L, const float *__restrict__ pop_all, double *__restrict__ out_all) {
     const int64_t N = (int64_t)L * L;
+    const float *pop = pop_all + (int64_t)blockIdx.y * Q2 * N;
+    double *out = out_all + (int64_t)blockIdx.y * 3 * N;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s >= N) return;
     const int x = (int)(s % L), y = (int)(s / L);
@@ -367,8 +376,10 @@ k2_snap(D2Desc D, const float *__restrict__ pop, double *__restrict__ out) {
 // Row transforms X_c[y][kx] = sum_x v_c[y][x] e^{-2 pi i kx x / L}: one
 // workgroup per (channel, row), twiddles cos, sin of 2 pi k / L.
 __global__ void __launch_bounds__(kBlock)
-k2_dft_rows(int L, const double *__restrict__ v, const double *__restrict__ twid, double2 *__restrict__ X) {
+k2_dft_rows(int L, const double *__restrict__ v_all, const double *__restrict__ twid, double2 *__restrict__ X_all) {
     __shared__ double row[2048], cs[2048], sn[2048];
+    const double *v = v_all + (int64_t)blockIdx.y * 3 * L * L;
+    double2 *X = X_all + (int64_t)blockIdx.y * 3 * L * L;
     const int64_t r = blockIdx.x;  // channel * L + y
     for (int x = threadIdx.x; x < L; x += kBlock) {
         row[x] = v[r * L + x];
@@ -393,8 +404,10 @@ k2_dft_rows(int L, const double *__restrict__ v, const double *__restrict__ twid
 // S += |rho_k|^2 / N, Jx, Jy += |j_a,k|^2 / N, and the projections of j_k on
 // k (longitudinal) and across it (transverse); k = 0 has no direction (0).
 __global__ void __launch_bounds__(kBlock)
-k2_dft_cols(int L, const double2 *__restrict__ X, const double *__restrict__ twid, double *__restrict__ acc) {
+k2_dft_cols(int L, const double2 *__restrict__ X_all, const double *__restrict__ twid, double *__restrict__ acc_all) {
     const int64_t N = (int64_t)L * L;
+    const double2 *X = X_all + (int64_t)blockIdx.y * 3 * N;
+    double *acc = acc_all + (int64_t)blockIdx.y * 5 * N;
     const int64_t o = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (o >= N) return;
     const int ky = (int)(o / L), kx = (int)(o - (int64_t)ky * L);
@@ -444,11 +457,93 @@ __device__ __forceinline__ void k2_fft_line(double2 *buf, int L, const double *_
     }
 }
 
+// The same butterflies on NL lines of L values side by side (line l at
+// buf + l * stride), one barrier per stage for all of them.
+template <int NL>
+__device__ __forceinline__ void k2_fft_lines(double2 *buf, int stride, int L, const double *__restrict__ twid) {
+    const int hl = L >> 1;
+    for (int len = 2; len <= L; len <<= 1) {
+        const int half = len >> 1, step = L / len;
+        for (int b = threadIdx.x; b < NL * hl; b += kBlock) {
+            const int line = b / hl, bb = b - line * hl;
+            const int grp = bb / half, j = bb - grp * half;
+            const int i0 = grp * len + j, i1 = i0 + half;
+            double2 *ln = buf + line * stride;
+            const double c = twid[j * step], sn = twid[L + j * step];
+            const double2 u = ln[i0], v = ln[i1];
+            const double tr = v.x * c + v.y * sn, ti = v.y * c - v.x * sn;  // v e^{-i theta}
+            ln[i0] = make_double2(u.x + tr, u.y + ti);
+            ln[i1] = make_double2(u.x - tr, u.y - ti);
+        }
+        __syncthreads();
+    }
+}
+
+// Power-of-two L <= kK2LinesMaxL: the density deviation and momentum of the
+// state (the sums of k2_snap, in its order) formed straight into bit-reversed
+// LDS lines and their three row transforms side by side, one workgroup per
+// (row, replica); then the three column transforms of a kx side by side.
+// The same values as k2_snap + k2_fft_rows + k2_fft_cols, without the
+// snapshot array and with a third of the barriers.
+// ML: the largest L of the instance (its LDS lines).
+constexpr int kK2LinesMaxL = 1024;
+template <int ML>
+__global__ void __launch_bounds__(kBlock)
+k2_snap_fft_rows(int L, int logL, const float *__restrict__ pop_all, const double *__restrict__ twid,
+                 double2 *__restrict__ X_all) {
+    __shared__ double2 buf[3 * ML];
+    const int64_t N = (int64_t)L * L;
+    const float *pop = pop_all + (int64_t)blockIdx.y * Q2 * N;
+    double2 *X = X_all + (int64_t)blockIdx.y * 3 * N;
+    const int y = blockIdx.x;
+    for (int x = threadIdx.x; x < L; x += kBlock) {
+        double r = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q2; ++i) {
+            const int xs = wrap2(x - c2x(i), L), ys = wrap2(y - c2y(i), L);
+            const double v = (double)pop[i * N + xs + (int64_t)L * ys];
+            r += v;
+            jx += c2x(i) * v;
+            jy += c2y(i) * v;
+        }
+        const int br = (int)(__brev((unsigned)x) >> (32 - logL));
+        buf[br] = make_double2(r, 0.0);
+        buf[L + br] = make_double2(jx, 0.0);
+        buf[2 * L + br] = make_double2(jy, 0.0);
+    }
+    __syncthreads();
+    k2_fft_lines<3>(buf, L, L, twid);
+    for (int kx = threadIdx.x; kx < L; kx += kBlock)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) X[ch * N + (int64_t)y * L + kx] = buf[ch * L + kx];
+}
+
+template <int ML>
+__global__ void __launch_bounds__(kBlock)
+k2_fft_cols3(int L, int logL, double2 *__restrict__ X_all, const double *__restrict__ twid) {
+    __shared__ double2 buf[3 * ML];
+    const int64_t N = (int64_t)L * L;
+    double2 *X = X_all + (int64_t)blockIdx.y * 3 * N;
+    const int kx = blockIdx.x;
+    for (int y = threadIdx.x; y < L; y += kBlock) {
+        const int br = (int)(__brev((unsigned)y) >> (32 - logL));
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) buf[ch * L + br] = X[ch * N + (int64_t)y * L + kx];
+    }
+    __syncthreads();
+    k2_fft_lines<3>(buf, L, L, twid);
+    for (int ky = threadIdx.x; ky < L; ky += kBlock)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) X[ch * N + (int64_t)ky * L + kx] = buf[ch * L + ky];
+}
+
 // Row FFTs X_c[y][kx] of the snapshot: one workgroup per (channel, row).
 __global__ void __launch_bounds__(kBlock)
-k2_fft_rows(int L, int logL, const double *__restrict__ v, const double *__restrict__ twid,
-            double2 *__restrict__ X) {
+k2_fft_rows(int L, int logL, const double *__restrict__ v_all, const double *__restrict__ twid,
+            double2 *__restrict__ X_all) {
     __shared__ double2 buf[2048];
+    const double *v = v_all + (int64_t)blockIdx.y * 3 * L * L;
+    double2 *X = X_all + (int64_t)blockIdx.y * 3 * L * L;
     const int64_t r = blockIdx.x;  // channel * L + y
     for (int x = threadIdx.x; x < L; x += kBlock)
         buf[__brev((unsigned)x) >> (32 - logL)] = make_double2(v[r * L + x], 0.0);
@@ -460,9 +555,10 @@ k2_fft_rows(int L, int logL, const double *__restrict__ v, const double *__restr
 // Column FFTs in place: X_c[ky][kx] from X_c[y][kx], one workgroup per
 // (channel, kx).
 __global__ void __launch_bounds__(kBlock)
-k2_fft_cols(int L, int logL, double2 *__restrict__ X, const double *__restrict__ twid) {
+k2_fft_cols(int L, int logL, double2 *__restrict__ X_all, const double *__restrict__ twid) {
     __shared__ double2 buf[2048];
     const int64_t N = (int64_t)L * L;
+    double2 *X = X_all + (int64_t)blockIdx.y * 3 * N;
     const int ch = blockIdx.x / L, kx = blockIdx.x - ch * L;
     double2 *col = X + ch * N + kx;
     for (int y = threadIdx.x; y < L; y += kBlock) buf[__brev((unsigned)y) >> (32 - logL)] = col[(int64_t)y * L];
@@ -474,8 +570,10 @@ k2_fft_cols(int L, int logL, double2 *__restrict__ X, const double *__restrict__
 // Accumulation of the spectra from the transformed channels, one thread per
 // (ky, kx): the same sums as the direct transform's.
 __global__ void __launch_bounds__(kBlock)
-k2_spec_acc(int L, const double2 *__restrict__ X, double *__restrict__ acc) {
+k2_spec_acc(int L, const double2 *__restrict__ X_all, double *__restrict__ acc_all) {
     const int64_t N = (int64_t)L * L;
+    const double2 *X = X_all + (int64_t)blockIdx.y * 3 * N;
+    double *acc = acc_all + (int64_t)blockIdx.y * 5 * N;
     const int64_t o = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (o >= N) return;
     const int ky = (int)(o / L), kx = (int)(o - (int64_t)ky * L);

@@ -97,6 +97,15 @@ __device__ __forceinline__ void pull_plane(const T *const (&qz)[Q], const PlaneO
 // Workgroup index to tile index: each XCD (workgroups are dealt to the 8
 // XCDs round-robin) gets one contiguous run of the tile table, whose tiles
 // are ordered x fastest, then y, then z, so neighbouring tiles share an L2.
+// s_waitcnt immediate (gfx9 encoding) that waits until at most n vector-memory
+// operations of the wave are outstanding (loads and stores alike, completed
+// in order), leaving the LDS and export counters free.  The staged kernels
+// wait with n = Q after a collision: the Q population stores of the wave are
+// then the only operations younger than the staged loads, which holds while
+// the kernel uses no scratch memory (build.py refuses a build where it does).
+constexpr unsigned vmcnt_wait(int n) { return (unsigned)((n & 15) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8)); }
+static_assert(vmcnt_wait(19) == 0x4F73 && vmcnt_wait(0) == 0x0F70, "s_waitcnt encoding");
+
 __device__ __forceinline__ int xcd_tile(int b, int nt) {
     const int per = nt / 8;
     if (b >= per * 8) return b;
@@ -489,8 +498,8 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     auto body = [&](int p, float(&ld)[Q], float(&cl)[Q]) __attribute__((always_inline)) {
         // 1. staged pulls of plane p have landed (stores of the last collision,
         //    if any, are the only younger memory operations)
-        if (stored_last) __builtin_amdgcn_s_waitcnt(0x4F73);  // vmcnt <= 19
-        else __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt == 0
+        if (stored_last) __builtin_amdgcn_s_waitcnt(vmcnt_wait(Q));  // the Q stores may still run
+        else __builtin_amdgcn_s_waitcnt(vmcnt_wait(0));
         __syncthreads();
         {
             float *rs = s_rho[rslot(p)];

@@ -377,8 +377,8 @@ k_meq_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ til
     auto body = [&](int p, float(&ld)[Q], float(&cl)[Q]) __attribute__((always_inline)) {
         // 1. the staged rows of plane p have landed (the stores of the last
         //    collision, if any, are the only younger memory operations)
-        if (stored_last) __builtin_amdgcn_s_waitcnt(0x4F73);  // vmcnt <= 19
-        else __builtin_amdgcn_s_waitcnt(0x0F70);              // vmcnt == 0
+        if (stored_last) __builtin_amdgcn_s_waitcnt(vmcnt_wait(Q));  // the Q stores may still run
+        else __builtin_amdgcn_s_waitcnt(vmcnt_wait(0));
         __syncthreads();
         {
             float *rs = s_rho[rslot(p)];

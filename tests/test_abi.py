@@ -78,7 +78,13 @@ def test_invalid_arguments_rejected_before_device(L):
                    (16, lbf.Params2(0, 0, 0, 1, 0, 1, 0, -1, 0))]:
         assert L.lb2_create(L_, ctypes.byref(p2), 1, ctypes.byref(h2)) == lbf.LB_EINVAL
     assert L.lb2_step(None, 1) == lbf.LB_EINVAL
-    assert L.lb2_spectra(None, None, None, None, None, None, None) == lbf.LB_EINVAL
+    assert L.lb2_spectra(None, 0, None, None, None, None, None, None) == lbf.LB_EINVAL
+    # batches: at least one replica, one sampling period
+    arr = (lbf.Params2 * 2)(lbf.Params2(0, 0, 0, 1, 0, 1, 0, 5, 0), lbf.Params2(0, 0, 0, 1, 0, 1, 0, 10, 0))
+    seeds = (ctypes.c_uint64 * 2)(1, 2)
+    assert L.lb2_create_batch(0, 16, arr, seeds, ctypes.byref(h2)) == lbf.LB_EINVAL
+    assert L.lb2_create_batch(2, 16, arr, seeds, ctypes.byref(h2)) == lbf.LB_EINVAL
+    assert L.lb2_create_batch(2, 3, arr, seeds, ctypes.byref(h2)) == lbf.LB_EINVAL
     bad_flag = lbf.make_params()
     bad_flag.flags = 4
     assert L.lb_create(16, ctypes.byref(bad_flag), 1, ctypes.byref(h)) == lbf.LB_EINVAL

@@ -154,3 +154,36 @@ def test_equilibrium_statistics_64():
         r = (sp[k] / n / prm["kT"]).reshape(-1)[1:]
         say(f"  {k}/kT mean {r.mean():.4f}")
         assert abs(r.mean() - 1) < 0.02, k
+
+
+@pytest.mark.parametrize("L", [48, 64])
+def test_batch_replicas_equal_single_handles(L):
+    """Replicas of one L in one handle (lb2_create_batch), each with its own
+    parameters and seed: fields and spectra bit for bit those of the same
+    replica alone (direct DFT spectra at L = 48, FFTs at L = 64), and one
+    replica against the oracle."""
+    lbf = require_gpu()
+    say(f"d2q9 batch L={L}")
+    seeds = [21, 22, 23, 24]
+    prms = [dict(PRM, sample_every=5), dict(PRM, a=0.05, sample_every=5), dict(PRM, kT=2e-5, sample_every=5),
+            dict(PRM, tau=0.7, b=0.2, sample_every=5)]
+    bat = lbf.Sim2D.batch(L, seeds, prms)
+    bat.step(23)
+    for r, (sd, p) in enumerate(zip(seeds, prms)):
+        one = lbf.Sim2D(L, sd, **p)
+        one.step(23)
+        fb, fo = bat.fields(f=True, replica=r), one.fields(f=True)
+        for k in ("rho", "j", "f"):
+            assert np.array_equal(fb[k], fo[k]), (r, k)
+        sb, so = bat.spectra(r), one.spectra()
+        assert sb["n_samples"] == so["n_samples"] == 4
+        for k in ("S", "Jx", "Jy", "Jpar", "Jperp"):
+            assert np.array_equal(sb[k], so[k]), (r, k)
+    o = D.Sim(L, seeds[2], **{k: v for k, v in prms[2].items() if k != "sample_every"})
+    o.step(23)
+    assert rel_err(bat.fields(f=True, replica=2)["f"], o.f) < 1e-5
+    # imports land in their own replica
+    f1 = bat.fields(f=True, replica=1)["f"]
+    bat.set_populations(bat.fields(f=True, replica=3)["f"], replica=1)
+    assert np.array_equal(bat.fields(f=True, replica=1)["f"], bat.fields(f=True, replica=3)["f"])
+    assert not np.array_equal(f1, bat.fields(f=True, replica=1)["f"])
