@@ -1611,16 +1611,19 @@ int lb2_step(lb2_sim *s, int64_t n) {
     const unsigned R = (unsigned)s->nrep;
     for (int64_t k = 0; k < n; ++k) {
         const int cur = (int)(s->t & 1);
-        hipLaunchKernelGGL(k2_step_tiled, dim3((unsigned)tiles * R), dim3(K2TX * K2TY), 0, s->stream,
-                           (const D2Desc *)s->d_desc, tiles, (const float *)s->pop[cur], s->pop[cur ^ 1], (uint64_t)s->t,
-                           s->d_err);
+        hipLaunchKernelGGL(s->nrep > 1 ? k2_step_tiled<true> : k2_step_tiled<false>, dim3((unsigned)tiles * R),
+                           dim3(K2TX * K2TY), 0, s->stream, s->D[0], (const D2Desc *)s->d_desc, tiles,
+                           (const float *)s->pop[cur], s->pop[cur ^ 1], (uint64_t)s->t, s->d_err);
         s->t += 1;
         if (s->sample_every > 0 && s->t % s->sample_every == 0) {
             const unsigned lines = (unsigned)(3 * s->L);
             const bool pow2 = (s->L & (s->L - 1)) == 0;
             int logL = 0;
             while ((1 << logL) < s->L) ++logL;
-            if (pow2 && s->L <= kK2LinesMaxL) {  // three lines per workgroup, no snapshot array
+            // batches: three lines per workgroup and no snapshot array (fewer,
+            // fuller workgroups; the same values as the passes below, which
+            // keep three times the workgroups for one latency-bound lattice)
+            if (pow2 && s->L <= kK2LinesMaxL && s->nrep > 1) {
                 const bool small = s->L <= 256;  // 12 KB of LDS lines instead of 48 KB
                 hipLaunchKernelGGL(small ? k2_snap_fft_rows<256> : k2_snap_fft_rows<kK2LinesMaxL>,
                                    dim3((unsigned)s->L, R), dim3(kBlock), 0, s->stream, s->L, logL,

@@ -208,16 +208,19 @@ __device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2],
 // A batch of replicas (one L, own parameters and seeds) is one launch: the
 // tiles of replica r follow those of replica r - 1, each replica's
 // populations a [9][L^2] block after the previous one's.
+// BATCH = false (one replica, the latency-bound small lattices): the
+// descriptor comes with the launch, no replica arithmetic, no descriptor load.
 constexpr int K2TX = 64, K2TY = 4;
+template <bool BATCH>
 __global__ void __launch_bounds__(K2TX * K2TY)
-k2_step_tiled(const D2Desc *__restrict__ descs, int tiles_per_rep, const float *__restrict__ pop_all,
+k2_step_tiled(D2Desc D0, const D2Desc *__restrict__ descs, int tiles_per_rep, const float *__restrict__ pop_all,
               float *__restrict__ pop_out_all, uint64_t t, int *__restrict__ err) {
     constexpr int EX = K2TX + 2;
     static_assert(2 * (K2TX + 2) + 2 * K2TY <= K2TX * K2TY, "one halo site per thread");
     __shared__ float s_rho[EX * (K2TY + 2)];
     const int gtile = xcd_tile(blockIdx.x, gridDim.x);
-    const int rep = gtile / tiles_per_rep, tile = gtile - rep * tiles_per_rep;
-    const D2Desc D = descs[rep];
+    const int rep = BATCH ? gtile / tiles_per_rep : 0, tile = gtile - rep * tiles_per_rep;
+    const D2Desc D = BATCH ? descs[rep] : D0;
     const int L = D.L;
     const int64_t N = (int64_t)L * L;
     const float *pop = pop_all + (int64_t)rep * Q2 * N;
