@@ -63,6 +63,12 @@ struct Words4 {
     uint32_t v[4];
 };
 
+// a ^ b ^ c as one three-input bitwise instruction (truth table 0x96); the
+// compiler forms it from no expression by itself
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -72,9 +78,16 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        c0 = hi1 ^ c1 ^ k0;
+        if (round < 2) {
+            // the collision noise's first two rounds still mix wave-uniform
+            // words (step, call, key): xor those on the scalar unit first
+            c0 = hi1 ^ (c1 ^ k0);
+            c2 = hi0 ^ (c3 ^ k1);
+        } else {
+            c0 = xor3(hi1, c1, k0);
+            c2 = xor3(hi0, c3, k1);
+        }
         c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
         c3 = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -87,10 +100,12 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return w;
 }
 
-// Uniform in (0,1): ((w >> 9) + 1/2) 2^-23, written as the odd 24-bit
-// integer ((w >> 8) | 1) times 2^-24 -- exact in FP32.
+// Uniform in (0,1): ((w >> 9) + 1/2) 2^-23.  The top 23 bits of w become the
+// mantissa of a float in [1, 2) (one funnel shift puts the exponent of 1
+// above them), and subtracting 1 - 2^-24 leaves (2 (w >> 9) + 1) 2^-24:
+// exact, since the difference has at most 24 significant bits.
 __device__ __forceinline__ float uniform01(uint32_t w) {
-    return (float)((w >> 8) | 1u) * 5.9604644775390625e-8f;
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u)) - 0.999999940395355224609375f;
 }
 
 // Box-Muller radius sqrt(-2 ln u) via the hardware base-2 logarithm.
