@@ -54,14 +54,16 @@ __host__ __device__ constexpr float n2(int a) {
 
 __device__ __forceinline__ int wrap2(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
 
-// Pulled deviations of site (x, y): d_i(r - c_i).
+// Pulled deviations of site (x, y): d_i(r - c_i).  The three source columns
+// x - c_x and the three source rows y - c_y are wrapped once; each pull is
+// then a 32-bit in-plane offset from the population's (uniform) base.
 __device__ __forceinline__ void pull2(const float *__restrict__ pop, int L, int x, int y, float (&d)[Q2]) {
-    const int64_t N = (int64_t)L * L;
+    const uint32_t N = (uint32_t)L * (uint32_t)L;
+    const uint32_t col[3] = {(uint32_t)wrap2(x + 1, L), (uint32_t)x, (uint32_t)wrap2(x - 1, L)};  // c_x = -1, 0, 1
+    const uint32_t row[3] = {(uint32_t)wrap2(y + 1, L) * (uint32_t)L, (uint32_t)y * (uint32_t)L,
+                             (uint32_t)wrap2(y - 1, L) * (uint32_t)L};  // c_y = -1, 0, 1
 #pragma unroll
-    for (int i = 0; i < Q2; ++i) {
-        const int xs = wrap2(x - c2x(i), L), ys = wrap2(y - c2y(i), L);
-        d[i] = pop[i * N + xs + (int64_t)L * ys];
-    }
+    for (int i = 0; i < Q2; ++i) d[i] = pop[(size_t)i * N + (col[c2x(i) + 1] + row[c2y(i) + 1])];
 }
 
 __device__ __forceinline__ float drho2(const float (&d)[Q2]) {
@@ -127,7 +129,7 @@ __device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2],
     const float p0 = rho * (D.a * dr + D.b * d2 * dr) - (0.5f * D.a * d2 + 0.25f * D.b * d2 * d2);
     const float cs2 = rho * (D.a + 3.0f * D.b * d2);
     // equilibrium moments (deviations from the rest state)
-    const float inv_rho = 1.0f / rho;
+    const float inv_rho = __builtin_amdgcn_rcpf(rho);  // hardware reciprocal, 1 ulp
     const float ux = m[1] * inv_rho, uy = m[2] * inv_rho;
     const float g2 = gx * gx + gy * gy, ug = ux * gx + uy * gy;
     const float S = p0 - D.kappa * rho * lap;
@@ -149,11 +151,12 @@ __device__ __forceinline__ bool k2_collide_site(const D2Desc &D, float (&d)[Q2],
     if (D.noise_amp > 0.0f) {
         const float A = 4.0f * (2.0f - 3.0f * cs2), C = 12.0f * (cs2 - 1.0f / 3.0f),
                     B = 16.0f * (1.25f - 0.75f * cs2);
-        // L83 scales normals only: the hardware reciprocal serves it
-        const float L33 = __builtin_sqrtf(A), L83 = C * __builtin_amdgcn_rcpf(L33), R = B - L83 * L83;
+        // the factor scales normals only: hardware square roots and
+        // reciprocal (1 ulp) serve it
+        const float L33 = __builtin_amdgcn_sqrtf(A), L83 = C * __builtin_amdgcn_rcpf(L33), R = B - L83 * L83;
         bad |= !(A > 0.0f) || !(R > 0.0f);
-        const float L88 = __builtin_sqrtf(R);
-        const float sig = D.noise_amp * __builtin_sqrtf(rho);
+        const float L88 = __builtin_amdgcn_sqrtf(R);
+        const float sig = D.noise_amp * __builtin_amdgcn_sqrtf(rho);
         const Words4 w0 = philox4x32_10(s, (uint32_t)t, 0u, (uint32_t)(t >> 32), D.key0, D.key1);
         const Words4 w1 = philox4x32_10(s, (uint32_t)t, 1u, (uint32_t)(t >> 32), D.key0, D.key1);
         const float r0 = bm_radius(uniform01(w0.v[0])), a0 = uniform01(w0.v[1]);
