@@ -57,6 +57,36 @@ def check_counted_waits(usage):
     return n
 
 
+# staged instances the host launches on large lattices and the waves per
+# SIMD each must keep: two 512-thread workgroups per CU on 64 x 8 tiles (the
+# FP32 snapshot instance is not launched there: sample steps of those plans
+# run on 64 x 4 tiles), three 256-thread ones on 64 x 4
+REQUIRED_OCCUPANCY = {
+    "_ZN5lbfss14k_fused_stagedIfLi64ELi8ELb1ELb0E": 4,
+    "_ZN5lbfss14k_fused_stagedI6__halfLi64ELi8ELb1ELb0E": 4,
+    "_ZN5lbfss14k_fused_stagedI6__halfLi64ELi8ELb1ELb1E": 4,
+    "_ZN5lbfss14k_fused_stagedIfLi64ELi4ELb1ELb0E": 3,
+    "_ZN5lbfss14k_fused_stagedIfLi64ELi4ELb1ELb1E": 3,
+}
+
+
+def check_occupancy(usage):
+    """Raise if a staged instance fell below the waves per SIMD its tiles
+    need (a VGPR count that crept up would halve its resident workgroups)."""
+    low = []
+    for prefix, need in REQUIRED_OCCUPANCY.items():
+        hits = [(k, v) for k, v in usage.items() if k.startswith(prefix)]
+        if not hits:
+            raise RuntimeError(f"no resource-usage remark for {prefix}")
+        for k, v in hits:
+            occ = int(v.get("Occupancy [waves/SIMD]", "0"))
+            if occ < need:
+                low.append(f"{k} ({v.get('VGPRs')} VGPRs, {occ} waves/SIMD, needs {need})")
+    if low:
+        raise RuntimeError("staged kernels below their occupancy: " + ", ".join(low))
+    return len(REQUIRED_OCCUPANCY)
+
+
 def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -69,9 +99,11 @@ def build(verbose: bool = False, extra=()) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stderr)
         raise subprocess.CalledProcessError(r.returncode, cmd)
-    n = check_counted_waits(resource_usage(r.stderr))
+    usage = resource_usage(r.stderr)
+    n = check_counted_waits(usage)
+    m = check_occupancy(usage)
     if verbose:
-        print(f"{n} staged kernel instances without scratch memory", flush=True)
+        print(f"{n} staged kernel instances without scratch memory, {m} at their occupancy", flush=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -135,6 +135,11 @@ struct lb_sim {
     FusedTile *d_tiles = nullptr;
     int n_tiles = 0;
     int tiles_for[3] = {0, 0, 0};
+    // sample steps of FP32 rows plans on 512-thread tiles run the snapshot
+    // kernel on tiles of its own (see rows_snap_tile)
+    FusedTile *d_tiles_snap = nullptr;
+    int n_tiles_snap = 0;
+    int snap_tiles_for[3] = {0, 0, 0};
 
     int64_t t = 0;
     lb_plan plan{LB_KERNEL_SPLIT, 0, 0, 0, 0, 0};
@@ -272,8 +277,12 @@ void launch_step(lb_sim *s, int cur, int koff, float *snap) {
         return;
     }
     if (s->plan.kernel == LB_KERNEL_ROWS && s->n_tiles > 0) {
-        launch_fused_staged<T, true>(s->d_desc, s->d_tiles, s->n_tiles, in, out, s->d_step, koff, s->d_err,
-                                     s->plan.tile_x, s->plan.tile_y, s->stream, snap, total);
+        if (snap && s->n_tiles_snap > 0)
+            launch_fused_staged<T, true>(s->d_desc, s->d_tiles_snap, s->n_tiles_snap, in, out, s->d_step, koff,
+                                         s->d_err, s->snap_tiles_for[0], s->snap_tiles_for[1], s->stream, snap, total);
+        else
+            launch_fused_staged<T, true>(s->d_desc, s->d_tiles, s->n_tiles, in, out, s->d_step, koff, s->d_err,
+                                         s->plan.tile_x, s->plan.tile_y, s->stream, snap, total);
         return;
     }
     if (s->plan.kernel == LB_KERNEL_STAGED && s->n_tiles > 0 && std::is_same<T, float>::value) {
@@ -723,6 +732,35 @@ int build_tiles(lb_sim *s, int tx, int ty, int tz) {
     s->tiles_for[0] = tx;
     s->tiles_for[1] = ty;
     s->tiles_for[2] = tz;
+    return LB_OK;
+}
+
+// The snapshot tile table of a plan: built where rows_snap_tile asks for one,
+// released otherwise (after the stream and any graph that reads it are done).
+int build_snap_tiles(lb_sim *s, const lb_plan &p) {
+    int tx = 0, ty = 0, tz = 0;
+    const bool want = p.kernel == LB_KERNEL_ROWS && !s->eq_pressure &&
+                      rows_snap_tile(s->hdesc, s->storage == LB_FP32, p.tile_x, p.tile_y, p.tile_z, tx, ty, tz);
+    if (want && s->d_tiles_snap && s->snap_tiles_for[0] == tx && s->snap_tiles_for[1] == ty &&
+        s->snap_tiles_for[2] == tz)
+        return LB_OK;
+    if (s->d_tiles_snap) {
+        HIPCHK(hipStreamSynchronize(s->stream));
+        drop_graph(s);
+        dev_release(s, s->d_tiles_snap, sizeof(FusedTile) * std::max<size_t>((size_t)s->n_tiles_snap, 1));
+        s->d_tiles_snap = nullptr;
+        s->n_tiles_snap = 0;
+        s->snap_tiles_for[0] = s->snap_tiles_for[1] = s->snap_tiles_for[2] = 0;
+    }
+    if (!want) return LB_OK;
+    std::vector<FusedTile> tiles;
+    if (make_fused_tiles(s->hdesc, tx, ty, tz, tiles) != 0) return LB_EINVAL;
+    int rc = upload(s, &s->d_tiles_snap, tiles);
+    if (rc) return rc;
+    s->n_tiles_snap = (int)tiles.size();
+    s->snap_tiles_for[0] = tx;
+    s->snap_tiles_for[1] = ty;
+    s->snap_tiles_for[2] = tz;
     return LB_OK;
 }
 
@@ -1283,6 +1321,7 @@ int lb_set_plan(lb_sim *s, const lb_plan *plan) {
     } else if (p.kernel != LB_KERNEL_SPLIT) {
         return LB_EINVAL;
     }
+    if (int rc = build_snap_tiles(s, p)) return rc;
     if (p.kernel != s->plan.kernel || p.tile_x != s->plan.tile_x || p.tile_y != s->plan.tile_y ||
         p.tile_z != s->plan.tile_z || p.graph_steps != s->plan.graph_steps)
         drop_graph(s);

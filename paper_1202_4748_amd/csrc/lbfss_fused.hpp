@@ -54,6 +54,16 @@ struct PlaneOffs {
     }
 };
 
+// A wave-uniform address pinned to scalar registers, so that an access at it
+// plus a 32-bit lane offset keeps no 64-bit per-lane address alive.
+template <typename P>
+__device__ __forceinline__ P *sbase(P *p) {
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    return (P *)(((uint64_t)hi << 32) | lo);
+}
+
 template <typename T>
 __device__ __forceinline__ float ldb(const T *p, uint32_t boff) {
     return Store<T>::ld((const T *)((const char *)p + boff), 0);
@@ -328,6 +338,9 @@ __device__ __forceinline__ uint32_t pull_off(int q, const PlaneOffs &o) {
 // rectangle entry at the site's row and at column ex + CH - 2 - cx_q.  The
 // rows mode issues about a quarter of the load instructions for the same
 // data.  Tiles of 512 threads (64 x 8) have eight waves; the rest four.
+// 512-thread tiles fit two workgroups per CU (LDS and at most 128 VGPRs)
+// in every instance the host launches; the build checks the VGPR count (a
+// launch-bounds hint to the same effect made the compiler's code slower)
 template <typename T, int TX, int TY, bool ROWS, bool SNAP>
 __global__ void __launch_bounds__(TX * TY)
 k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ tiles, const T *__restrict__ pop,
@@ -436,10 +449,12 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
     const bool wave_stores = __builtin_amdgcn_readfirstlane((int)(__ballot(inner) != 0)) != 0;
 
     // rows mode: the chunks this lane copies, one per 64-lane slice m of the
-    // NL chunks of a population: byte offsets of its column and of its row
-    // for the three y shifts (cy = -1, 0, 1)
-    uint32_t r_col[NM], r_row[NM][3];
+    // NL chunks of a population: byte offsets of its column and of its
+    // unshifted row; the rows one above or below (y shifts cy = -1, 1) are
+    // wrapped from it where a load needs them
+    uint32_t r_col[NM], r_row[NM];
     bool r_on[NM];
+    const uint32_t row_bytes = (uint32_t)L * sizeof(T), plane_bytes = LL * sizeof(T);
     if (ROWS) {
         const int lane = tid & 63;
 #pragma unroll
@@ -448,11 +463,15 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
             r_on[m] = j < NL;
             const int ey = j / CW, k = j - (j / CW) * CW;
             r_col[m] = (uint32_t)(((tl.x0 - CH + CH * k) % L + L) % L) * sizeof(T);
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                r_row[m][c] = (uint32_t)(((tl.y0 - 2 + ey - (c - 1)) % L + L) % L) * (uint32_t)L * sizeof(T);
+            r_row[m] = (uint32_t)(((tl.y0 - 2 + ey) % L + L) % L) * row_bytes;
         }
     }
+    // byte offset of the source row of a pull with y shift cy (row - cy)
+    auto row_of = [&](uint32_t r, int cy) {
+        if (cy > 0) return r == 0 ? plane_bytes - row_bytes : r - row_bytes;
+        if (cy < 0) return r + row_bytes == plane_bytes ? 0u : r + row_bytes;
+        return r;
+    };
 
     auto issue = [&](int p) __attribute__((always_inline)) {
         const int zc = wrap_near(p, L);
@@ -467,7 +486,7 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
 #pragma unroll
                 for (int m = 0; m < NM; ++m)
                     if (r_on[m])
-                        __builtin_amdgcn_global_load_lds((gptr_t)(bq + r_row[m][cy_of(q) + 1] + r_col[m]),
+                        __builtin_amdgcn_global_load_lds((gptr_t)(bq + (row_of(r_row[m], cy_of(q)) + r_col[m])),
                                                          (lptr_t)&s_stage[q][m * 64 * CH], 16, 0, 0);
             } else {
                 __builtin_amdgcn_global_load_lds((gptr_t)(bq + pull_off(q, io)), (lptr_t)&s_stage[q][wave * 64], 4,
@@ -507,6 +526,20 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
 #pragma unroll
                 for (int q = 0; q < Q; ++q) ld[q] = Store<T>::ld(s_stage[q], slot_in(q));
                 rs[r_in] = drho_of(ld);
+                // the sample snapshot of the pulled state of plane p (its
+                // collision comes two iterations later, at the register peak)
+                if constexpr (SNAP)
+                    if (p >= tl.z0 && p < tl.z0 + tl.nz) {
+                        // plane bases of the four snapshot arrays in scalar
+                        // registers, the lane's in-plane offset added per store
+                        float jx, jy, jz;
+                        momentum_of(ld, jx, jy, jz);
+                        const float *sp = snap + d.site_off + (int64_t)p * LL;
+                        const float v[4] = {drho_of(ld), jx, jy, jz};
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            *(float *)((char *)sbase(sp + c * total) + site_c * 4u) = v[c];
+                    }
             }
             if (has_h) {
                 float h[Q];
@@ -562,7 +595,6 @@ k_fused_staged(const RepDesc *__restrict__ desc, const FusedTile *__restrict__ t
                 }
                 const uint32_t s = site_c + (uint32_t)z * LL;
                 const SiteNoise noise{s, (uint32_t)t, (uint32_t)(t >> 32), d.key0, d.key1};
-                if constexpr (SNAP) write_snapshot(snap, total, d.site_off + (int64_t)s, cl);
                 const float rho = collide_site(d, cl, Fx, Fy, Fz, noise);
                 bad |= !(rho > 0.0f && rho < 1e30f);  // Sec. III B: rho must stay positive
                 T *oz = obase + (uint32_t)z * LL;
@@ -681,9 +713,25 @@ inline bool staged_tile_ok(int tx, int ty) {
 
 // the rows staging also takes 64 x 4 tiles (two halo sites for some threads)
 // and 64 x 8 tiles (512 threads: fewer halo rows per site; two workgroups
-// per CU with FP16 storage, one with FP32)
+// per CU)
 inline bool rows_tile_ok(int tx, int ty) {
     return staged_tile_ok(tx, ty) || (tx == 64 && ty == 4) || (tx == 64 && ty == 8);
+}
+
+// With FP32 storage the snapshot instance of the 512-thread rows kernel needs
+// more than the 128 VGPRs of two workgroups per CU, so the sample steps of
+// such a plan run on 64 x 4 tiles (three workgroups per CU; every tile shape
+// gives the same bits), in three z slabs on large lattices.  Returns whether
+// the plan (tx, ty, tz) takes such a table, and its shape.
+inline bool rows_snap_tile(const std::vector<RepDesc> &reps, bool fp32, int tx, int ty, int tz, int &sx, int &sy,
+                           int &sz) {
+    if (!fp32 || tx * ty != 512) return false;
+    int maxL = 0;
+    for (const auto &d : reps) maxL = std::max(maxL, d.L);
+    sx = 64;
+    sy = 4;
+    sz = maxL >= 128 ? (maxL + 2) / 3 : tz;
+    return true;
 }
 
 

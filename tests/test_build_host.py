@@ -29,3 +29,23 @@ def test_scratch_in_a_staged_kernel_fails():
         build.check_counted_waits(build.resource_usage(bad))
     with pytest.raises(RuntimeError):
         build.check_counted_waits({})
+
+
+def _occ_remarks(fp32_64x8_waves):
+    lines = []
+    for prefix, need in build.REQUIRED_OCCUPANCY.items():
+        occ = fp32_64x8_waves if prefix.endswith("IfLi64ELi8ELb1ELb0E") else need
+        lines.append(f"x.hip:1:1: remark: Function Name: {prefix}EEvv [-Rpass-analysis=kernel-resource-usage]")
+        lines.append(f"x.hip:1:1: remark:     Occupancy [waves/SIMD]: {occ} [-Rpass-analysis=kernel-resource-usage]")
+    return "\n".join(lines) + "\n"
+
+
+def test_occupancy_guard():
+    """The 64 x 8 FP32 step kernel must keep four waves per SIMD (two
+    512-thread workgroups per CU); one VGPR too many (three waves) fails the
+    build, as does a missing remark."""
+    assert build.check_occupancy(build.resource_usage(_occ_remarks(4))) == len(build.REQUIRED_OCCUPANCY)
+    with pytest.raises(RuntimeError, match="below their occupancy"):
+        build.check_occupancy(build.resource_usage(_occ_remarks(3)))
+    with pytest.raises(RuntimeError, match="no resource-usage remark"):
+        build.check_occupancy({})

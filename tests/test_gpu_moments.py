@@ -128,3 +128,32 @@ def test_sample_timing_does_not_change_results(kernel, graph):
     ka, kb = a.sk3(), b.sk3()
     assert ka["n_samples"] == kb["n_samples"] == 4 and np.array_equal(ka["sum_C"], kb["sum_C"])
     assert ma["series"][:, 0].tolist() == [5.0 * (i + 1) for i in range(8)]
+
+
+@pytest.mark.parametrize("L,tz", [(40, 7), (128, 32)])
+def test_fp32_512_thread_tiles_sample_on_their_own_tiles(L, tz):
+    """FP32 rows plans on 64 x 8 tiles (512 threads) take their samples with
+    the snapshot kernel on a 64 x 4 tile table of its own (three z slabs from
+    L = 128 on, the plan's slabs below; L = 40 leaves partial tiles): the
+    fields, accumulators, histograms and series equal those of a 64 x 4 plan
+    and of the split passes bit for bit, with direct launches and graphs."""
+    lbf = require_gpu()
+    say(f"fp32 64x8 sampling L={L} tz={tz}")
+    prm = dict(M0, sample_every=5, series_capacity=16, hist_bins=32, hist_range=0.05)
+    runs = []
+    for kernel, tile, g in [("split", (0, 0, 0), 0), ("rows", (64, 4, tz), 0), ("rows", (64, 8, tz), 0),
+                            ("rows", (64, 8, tz), 10)]:
+        s_ = lbf.Sim(L, 43, **prm)
+        s_.set_plan(kernel, tile, g)
+        s_.step(30)
+        runs.append((s_.fields(f=True)["f"], s_.moments(series=True), s_.histogram()))
+    f0, m0, h0 = runs[0]
+    assert m0["n_samples"] == 6
+    for f, m, h in runs[1:]:
+        assert np.array_equal(f, f0)
+        assert m["n_samples"] == m0["n_samples"]
+        for la, lb_ in zip(m["levels"], m0["levels"]):
+            for k in ("m", "m2", "m3", "m4", "abs_m", "E", "E2"):
+                assert la[k] == lb_[k], (la["Lb"], k)
+        assert np.array_equal(m["sk"], m0["sk"]) and np.array_equal(m["series"], m0["series"])
+        assert np.array_equal(h, h0)
