@@ -157,3 +157,30 @@ def test_fp32_512_thread_tiles_sample_on_their_own_tiles(L, tz):
                 assert la[k] == lb_[k], (la["Lb"], k)
         assert np.array_equal(m["sk"], m0["sk"]) and np.array_equal(m["series"], m0["series"])
         assert np.array_equal(h, h0)
+
+
+def test_fp32_512_thread_tiles_sample_in_a_batch():
+    """A batch of FP32 replicas of different sizes on a 64 x 8 rows plan with
+    graphs: its sample steps run on the snapshot tile table sized from the
+    largest lattice (here 128: three slabs of 43 planes); every replica's
+    fields, accumulators and series equal those of its lone handle (which
+    samples on a 64 x 4 plan) bit for bit."""
+    lbf = require_gpu()
+    say("fp32 64x8 sampling in a batch")
+    Ls, seeds = [128, 40, 64], [51, 52, 53]
+    prms = [dict(M0, sample_every=5, series_capacity=16) for _ in Ls]
+    prms[1]["a"] = 0.02
+    bat = lbf.Sim.batch(Ls, seeds, prms)
+    bat.set_plan("rows", (64, 8, 32), 10)
+    bat.step(30)
+    for r, (L, sd, p) in enumerate(zip(Ls, seeds, prms)):
+        one = lbf.Sim(L, sd, **p)
+        one.set_plan("rows", (64, 4, 16), 0)
+        one.step(30)
+        assert np.array_equal(bat.fields(r, f=True)["f"], one.fields(f=True)["f"]), r
+        mb, mo = bat.moments(r, series=True), one.moments(series=True)
+        assert mb["n_samples"] == mo["n_samples"] == 6
+        for la, lb_ in zip(mb["levels"], mo["levels"]):
+            for k in ("m", "m2", "m3", "m4", "abs_m", "E", "E2"):
+                assert la[k] == lb_[k], (r, la["Lb"], k)
+        assert np.array_equal(mb["sk"], mo["sk"]) and np.array_equal(mb["series"], mo["series"]), r
