@@ -331,7 +331,7 @@ void launch_snapshot(lb_sim *s, int cur) {
 void enqueue_reductions(lb_sim *s) {
     hipLaunchKernelGGL(k_rows, dim3((unsigned)ceil_div(s->n_rows, kBlock / 64)), dim3(kBlock), 0, s->stream,
                        s->d_sd, s->d_cum_rows, s->nrep, s->total_sites, (const float *)s->d_snap, s->d_ws);
-    hipLaunchKernelGGL(k_cols, dim3((unsigned)ceil_div(s->n_cols, kBlock)), dim3(kBlock), 0, s->stream,
+    hipLaunchKernelGGL(k_cols, dim3((unsigned)ceil_div(s->n_cols, 64)), dim3(kBlock), 0, s->stream,
                        s->d_sd, s->d_cum_cols, s->nrep, (const float *)s->d_snap, s->d_ws);
     hipLaunchKernelGGL(k_planes, dim3((unsigned)ceil_div(s->n_planes, kBlock / 64)), dim3(kBlock), 0, s->stream,
                        s->d_sd, s->d_cum_planes, s->nrep, s->d_ws);

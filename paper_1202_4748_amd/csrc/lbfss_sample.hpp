@@ -135,25 +135,37 @@ k_rows(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nre
     }
 }
 
-// 3. Column sums over y of drho for every (z, x).
+// 3. Column sums over y of drho for every (z, x): a workgroup takes 64
+// consecutive columns (one per lane, so each load reads 64 consecutive
+// values) and its four waves the four interleaved y phases y = k, k + 4, ...
+// (the rows past the last multiple of four go to phase 0); the phase sums
+// combine as (a0 + a1) + (a2 + a3).
 __global__ void __launch_bounds__(kBlock)
 k_cols(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep,
        const float *__restrict__ snap, double *__restrict__ ws) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= cum[nrep]) return;
-    const int r = find_cum(cum, nrep, g);
-    const SampDesc &s = sd[r];
-    const int64_t li = g - cum[r];
-    const int L = s.L;
-    const int64_t z = li / L, x = li - z * L;
-    const float *col = snap + s.site_off + x + (int64_t)L * L * z;
-    double a[4] = {0.0, 0.0, 0.0, 0.0};  // fixed interleave: deterministic, four loads in flight
-    int y = 0;
-    for (; y + 3 < L; y += 4)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) a[k] += (double)col[(int64_t)(y + k) * L];
-    for (; y < L; ++y) a[0] += (double)col[(int64_t)y * L];
-    ws[s.cols_off + li] = (a[0] + a[1]) + (a[2] + a[3]);
+    static_assert(kBlock == 4 * 64, "one wave per y phase");
+    __shared__ double sh[4][64];
+    const int lane = threadIdx.x & 63, k = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * 64 + lane;
+    const bool on = g < cum[nrep];
+    double a = 0.0;
+    int r = 0;
+    int64_t li = 0;
+    if (on) {
+        r = find_cum(cum, nrep, g);
+        const SampDesc &s = sd[r];
+        li = g - cum[r];
+        const int L = s.L;
+        const int64_t z = li / L, x = li - z * L;
+        const float *col = snap + s.site_off + x + (int64_t)L * L * z;
+        int y = 0;
+        for (; y + 3 < L; y += 4) a += (double)col[(int64_t)(y + k) * L];
+        if (k == 0)
+            for (; y < L; ++y) a += (double)col[(int64_t)y * L];
+    }
+    sh[k][lane] = a;
+    __syncthreads();
+    if (k == 0 && on) ws[sd[r].cols_off + li] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
 }
 
 // 4. Plane sums: one 64-lane wave per (replica, plane family, n) over six
@@ -365,6 +377,8 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
     const double dbar = gl[0], inv_rho0 = 1.0 / gl[1];
     const int Lb = s.lev_L[c.lev];
     const double n = (double)Lb * (double)Lb * (double)Lb;
+    // box volume reciprocals, once per chunk (exact for power-of-two boxes)
+    const double inv_n = 1.0 / n, inv_2n = 0.5 * inv_n;
     const int64_t nbl = s.L / Lb;
     const int64_t cnt = nbl * nbl * nbl;
     const bool from_snap = c.lev == s.snap_lev;  // one-site boxes: the snapshot itself
@@ -385,7 +399,7 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
         }
         const double sphi = (B1 - n * dbar) * inv_rho0;
         const double sphi2 = (B2 - 2.0 * dbar * B1 + n * dbar * dbar) * inv_rho0 * inv_rho0;
-        const double m = sphi / n, E = sphi2 / (2.0 * n);
+        const double m = sphi * inv_n, E = sphi2 * inv_2n;
         const double m2 = m * m;
         acc[0] += m;
         acc[1] += m2;
@@ -458,14 +472,20 @@ k_level_reduce(const SampDesc *__restrict__ sd, int max_nlev, double *__restrict
     const SampDesc &s = sd[r];
     if (lev >= s.nlev) return;  // whole workgroup
     double *acc = acc_all + s.acc_off;
+    // one pass over the chunks for all moments (each moment still adds its
+    // chunks in the same order per thread, then the same block sum)
+    double v[kMoments] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k = threadIdx.x; k < s.chunk_count[lev]; k += kBlock) {
+        const double *pk = parts + (s.chunk_first[lev] + k) * kMoments;
+#pragma unroll
+        for (int q = 0; q < kMoments; ++q) v[q] += pk[q];
+    }
+#pragma unroll
     for (int q = 0; q < kMoments; ++q) {
-        double v = 0.0;
-        for (int64_t k = threadIdx.x; k < s.chunk_count[lev]; k += kBlock)
-            v += parts[(s.chunk_first[lev] + k) * kMoments + q];
-        v = block_sum(v, sh);
+        const double t = block_sum(v[q], sh);
         if (threadIdx.x == 0) {
-            ws[s.levtot_off + lev * kMoments + q] = v;
-            acc[lev * kMoments + q] += v;
+            ws[s.levtot_off + lev * kMoments + q] = t;
+            acc[lev * kMoments + q] += t;
         }
     }
 }
