@@ -167,7 +167,8 @@ enum {
                            * (FP32 storage; FP16 handles run FUSED) */
     LB_KERNEL_ROWS = 3    /* as STAGED, the staging copies the source rows of each population
                            * with 16-byte loads (FP32 or FP16 storage); every L a multiple
-                           * of 4 (FP32) or 8 (FP16), else LB_EINVAL */
+                           * of 4 (FP32) or 8 (FP16), else LB_EINVAL.  FP32 plans on 64 x 8
+                           * tiles run their sample steps on 64 x 4 tiles (same results) */
 };
 
 typedef struct {
@@ -197,10 +198,11 @@ typedef struct lb_sim lb_sim; /* opaque, owned by the library */
  * (site, 0, 1 << 16, 0), u = 0, f_i = w_i rho.  *out receives the handle
  * (owned by the library until lb_destroy); p is read during the call only.
  * Initial plan: LB_KERNEL_ROWS where every L allows it (else FUSED, or SPLIT
- * with LB_EQ_PRESSURE); when the largest L is at least 128, on 64 x 4 tiles
- * in three z slabs (FP32), 64 x 8 tiles in six (FP16) or 64 x 8 tiles in
- * eight (LB_EQ_PRESSURE), else on 32 x 8 tiles; direct launches
- * (lb_set_plan and lb_tune change it; results do not depend on it).
+ * with LB_EQ_PRESSURE); when the largest L is at least 256 (FP32) on 64 x 8
+ * tiles in four z slabs, from 128 to 255 (FP32) on 64 x 4 tiles in three,
+ * from 128 (FP16) on 64 x 8 tiles in six, from 128 (LB_EQ_PRESSURE) on 64 x 8
+ * tiles in eight, else on 32 x 8 tiles; direct launches (lb_set_plan and
+ * lb_tune change it; results do not depend on it).
  * Errors: LB_EINVAL for L < 4, L > 1024, tau <= 1/2, kT < 0, kappa < 0,
  * b < 0, rho_c <= 0, init_sigma < 0, bad storage, flags, sample_every < 0,
  * n_levels < 0 or series_capacity < 0; LB_ENOMEM; LB_EDEVICE. */
