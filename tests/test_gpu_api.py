@@ -30,6 +30,26 @@ def test_info_reports_the_handle():
     assert (i["kernel"], i["tile_x"], i["tile_y"], i["tile_z"]) == (p["kernel"], p["tile_x"], p["tile_y"], p["tile_z"])
 
 
+def test_plan_changes_release_their_tables():
+    """Switching plans frees the tile tables it no longer needs (the rows
+    table and, for FP32 64 x 8 plans, the 64 x 4 table of their sample
+    steps): device memory is the same after any number of switches."""
+    lbf = require_gpu()
+    sim = lbf.Sim(64, 4, sample_every=5, **M0)
+    plans = [("rows", (64, 8, 16)), ("rows", (64, 4, 16)), ("split", (0, 0, 0)), ("rows", (64, 8, 32)),
+             ("fused", (32, 8, 16))]
+    sim.set_plan(*plans[0])
+    sim.step(5)
+    first = None
+    for rnd in range(3):
+        for k, t in plans:
+            sim.set_plan(k, t)
+            sim.step(5)
+        b = sim.info()["device_bytes"]
+        first = b if first is None else first
+        assert b == first, (rnd, b, first)
+
+
 def test_step_count_zero_and_negative():
     lbf = require_gpu()
     sim = lbf.Sim(8, 3, **M0)
