@@ -1666,14 +1666,20 @@ int lb2_step(lb2_sim *s, int64_t n) {
             // fuller workgroups; the same values as the passes below, which
             // keep three times the workgroups for one latency-bound lattice)
             if (pow2 && s->L <= kK2LinesMaxL && s->nrep > 1) {
-                const bool small = s->L <= 256;  // 12 KB of LDS lines instead of 48 KB
+                const bool small = s->L <= 256;  // LDS lines sized for L = 256
                 hipLaunchKernelGGL(small ? k2_snap_fft_rows<256> : k2_snap_fft_rows<kK2LinesMaxL>,
                                    dim3((unsigned)s->L, R), dim3(kBlock), 0, s->stream, s->L, logL,
                                    (const float *)s->pop[cur ^ 1], (const double *)s->d_twid, s->d_X);
-                hipLaunchKernelGGL(small ? k2_fft_cols3<256> : k2_fft_cols3<kK2LinesMaxL>, dim3((unsigned)s->L, R),
-                                   dim3(kBlock), 0, s->stream, s->L, logL, s->d_X, (const double *)s->d_twid);
-                hipLaunchKernelGGL(k2_spec_acc, dim3(nb, R), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
-                                   s->d_acc);
+                // columns: four adjacent kx per workgroup up to L = 256 (48 KB of
+                // LDS lines), one above, the spectra accumulated in the same pass
+                if (small)
+                    hipLaunchKernelGGL((k2_fft_cols3_acc<256, 4>), dim3((unsigned)s->L / 4, R), dim3(kBlock), 0,
+                                       s->stream, s->L, logL, (const double2 *)s->d_X, (const double *)s->d_twid,
+                                       s->d_acc);
+                else
+                    hipLaunchKernelGGL((k2_fft_cols3_acc<kK2LinesMaxL, 1>), dim3((unsigned)s->L, R), dim3(kBlock), 0,
+                                       s->stream, s->L, logL, (const double2 *)s->d_X, (const double *)s->d_twid,
+                                       s->d_acc);
                 s->n_samples += 1;
                 continue;
             }

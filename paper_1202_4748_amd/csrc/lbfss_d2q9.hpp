@@ -488,9 +488,9 @@ __device__ __forceinline__ void k2_fft_lines(double2 *buf, int stride, int L, co
 // Power-of-two L <= kK2LinesMaxL: the density deviation and momentum of the
 // state (the sums of k2_snap, in its order) formed straight into bit-reversed
 // LDS lines and their three row transforms side by side, one workgroup per
-// (row, replica); then the three column transforms of a kx side by side.
-// The same values as k2_snap + k2_fft_rows + k2_fft_cols, without the
-// snapshot array and with a third of the barriers.
+// (row, replica); k2_fft_cols3_acc then takes the columns.  The same values
+// as k2_snap + k2_fft_rows, without the snapshot array and with a third of
+// the barriers.
 // ML: the largest L of the instance (its LDS lines).
 constexpr int kK2LinesMaxL = 1024;
 template <int ML>
@@ -524,25 +524,6 @@ k2_snap_fft_rows(int L, int logL, const float *__restrict__ pop_all, const doubl
         for (int ch = 0; ch < 3; ++ch) X[ch * N + (int64_t)y * L + kx] = buf[ch * L + kx];
 }
 
-template <int ML>
-__global__ void __launch_bounds__(kBlock)
-k2_fft_cols3(int L, int logL, double2 *__restrict__ X_all, const double *__restrict__ twid) {
-    __shared__ double2 buf[3 * ML];
-    const int64_t N = (int64_t)L * L;
-    double2 *X = X_all + (int64_t)blockIdx.y * 3 * N;
-    const int kx = blockIdx.x;
-    for (int y = threadIdx.x; y < L; y += kBlock) {
-        const int br = (int)(__brev((unsigned)y) >> (32 - logL));
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) buf[ch * L + br] = X[ch * N + (int64_t)y * L + kx];
-    }
-    __syncthreads();
-    k2_fft_lines<3>(buf, L, L, twid);
-    for (int ky = threadIdx.x; ky < L; ky += kBlock)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) X[ch * N + (int64_t)ky * L + kx] = buf[ch * L + ky];
-}
-
 // Row FFTs X_c[y][kx] of the snapshot: one workgroup per (channel, row).
 __global__ void __launch_bounds__(kBlock)
 k2_fft_rows(int L, int logL, const double *__restrict__ v_all, const double *__restrict__ twid,
@@ -573,6 +554,26 @@ k2_fft_cols(int L, int logL, double2 *__restrict__ X_all, const double *__restri
     for (int ky = threadIdx.x; ky < L; ky += kBlock) col[(int64_t)ky * L] = buf[ky];
 }
 
+// The spectra of mode (ky, kx) from its transformed channels (density, jx,
+// jy), added to the accumulators at o = ky L + kx: |rho_k|^2, |jx_k|^2,
+// |jy_k|^2 and the projections of j_k on k (longitudinal) and across it
+// (transverse), each divided by N; k = 0 has no direction (0).
+__device__ __forceinline__ void k2_spec_add(double *acc, int64_t N, int L, int ky, int kx, const double (&re)[3],
+                                            const double (&im)[3]) {
+    const int64_t o = (int64_t)ky * L + kx;
+    const double inv = 1.0 / (double)N;
+    const int mx = kx <= L / 2 ? kx : kx - L, my = ky <= L / 2 ? ky : ky - L;
+    const double kn = sqrt((double)mx * mx + (double)my * my);
+    const double hx = kn > 0 ? mx / kn : 0.0, hy = kn > 0 ? my / kn : 0.0;
+    const double pr = hx * re[1] + hy * re[2], pi = hx * im[1] + hy * im[2];
+    const double tr = -hy * re[1] + hx * re[2], ti = -hy * im[1] + hx * im[2];
+    acc[o] += (re[0] * re[0] + im[0] * im[0]) * inv;
+    acc[N + o] += (re[1] * re[1] + im[1] * im[1]) * inv;
+    acc[2 * N + o] += (re[2] * re[2] + im[2] * im[2]) * inv;
+    acc[3 * N + o] += (pr * pr + pi * pi) * inv;
+    acc[4 * N + o] += (tr * tr + ti * ti) * inv;
+}
+
 // Accumulation of the spectra from the transformed channels, one thread per
 // (ky, kx): the same sums as the direct transform's.
 __global__ void __launch_bounds__(kBlock)
@@ -590,17 +591,41 @@ k2_spec_acc(int L, const double2 *__restrict__ X_all, double *__restrict__ acc_a
         re[ch] = v.x;
         im[ch] = v.y;
     }
-    const double inv = 1.0 / (double)N;
-    const int mx = kx <= L / 2 ? kx : kx - L, my = ky <= L / 2 ? ky : ky - L;
-    const double kn = sqrt((double)mx * mx + (double)my * my);
-    const double hx = kn > 0 ? mx / kn : 0.0, hy = kn > 0 ? my / kn : 0.0;
-    const double pr = hx * re[1] + hy * re[2], pi = hx * im[1] + hy * im[2];
-    const double tr = -hy * re[1] + hx * re[2], ti = -hy * im[1] + hx * im[2];
-    acc[o] += (re[0] * re[0] + im[0] * im[0]) * inv;
-    acc[N + o] += (re[1] * re[1] + im[1] * im[1]) * inv;
-    acc[2 * N + o] += (re[2] * re[2] + im[2] * im[2]) * inv;
-    acc[3 * N + o] += (pr * pr + pi * pi) * inv;
-    acc[4 * N + o] += (tr * tr + ti * ti) * inv;
+    k2_spec_add(acc, N, L, ky, kx, re, im);
+}
+
+// Batches: the column transforms of CPW adjacent kx (three channels each,
+// 3 CPW lines side by side; each row read as CPW consecutive values) and the
+// spectra accumulated straight from LDS, without writing the columns back:
+// per line the butterflies of k2_fft_cols, per mode the sums of k2_spec_acc.
+template <int ML, int CPW>
+__global__ void __launch_bounds__(kBlock)
+k2_fft_cols3_acc(int L, int logL, const double2 *__restrict__ X_all, const double *__restrict__ twid,
+                 double *__restrict__ acc_all) {
+    __shared__ double2 buf[3 * CPW * ML];
+    const int64_t N = (int64_t)L * L;
+    const double2 *X = X_all + (int64_t)blockIdx.y * 3 * N;
+    double *acc = acc_all + (int64_t)blockIdx.y * 5 * N;
+    const int kx0 = blockIdx.x * CPW;
+    for (int i = threadIdx.x; i < L * CPW; i += kBlock) {
+        const int y = i / CPW, c = i - y * CPW;
+        const int br = (int)(__brev((unsigned)y) >> (32 - logL));
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) buf[(ch * CPW + c) * L + br] = X[ch * N + (int64_t)y * L + kx0 + c];
+    }
+    __syncthreads();
+    k2_fft_lines<3 * CPW>(buf, L, L, twid);
+    for (int i = threadIdx.x; i < L * CPW; i += kBlock) {
+        const int ky = i / CPW, c = i - ky * CPW;
+        double re[3], im[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const double2 v = buf[(ch * CPW + c) * L + ky];
+            re[ch] = v.x;
+            im[ch] = v.y;
+        }
+        k2_spec_add(acc, N, L, ky, kx0 + c, re, im);
+    }
 }
 
 }  // namespace lbfss
