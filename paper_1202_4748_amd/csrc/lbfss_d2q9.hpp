@@ -540,18 +540,27 @@ k2_fft_rows(int L, int logL, const double *__restrict__ v_all, const double *__r
 }
 
 // Column FFTs in place: X_c[ky][kx] from X_c[y][kx], one workgroup per
-// (channel, kx).
+// (channel, CPW adjacent kx; each row read as CPW consecutive values), the
+// butterflies of k2_fft_line on each column.
+template <int CPW>
 __global__ void __launch_bounds__(kBlock)
 k2_fft_cols(int L, int logL, double2 *__restrict__ X_all, const double *__restrict__ twid) {
-    __shared__ double2 buf[2048];
+    __shared__ double2 buf[CPW * 2048];
     const int64_t N = (int64_t)L * L;
     double2 *X = X_all + (int64_t)blockIdx.y * 3 * N;
-    const int ch = blockIdx.x / L, kx = blockIdx.x - ch * L;
-    double2 *col = X + ch * N + kx;
-    for (int y = threadIdx.x; y < L; y += kBlock) buf[__brev((unsigned)y) >> (32 - logL)] = col[(int64_t)y * L];
+    const int per = L / CPW, ch = blockIdx.x / per, kx0 = (blockIdx.x - ch * per) * CPW;
+    double2 *col = X + ch * N + kx0;
+    for (int i = threadIdx.x; i < L * CPW; i += kBlock) {
+        const int y = i / CPW, c = i - y * CPW;
+        buf[c * L + (__brev((unsigned)y) >> (32 - logL))] = col[(int64_t)y * L + c];
+    }
     __syncthreads();
-    k2_fft_line(buf, L, twid);
-    for (int ky = threadIdx.x; ky < L; ky += kBlock) col[(int64_t)ky * L] = buf[ky];
+    if constexpr (CPW == 1) k2_fft_line(buf, L, twid);
+    else k2_fft_lines<CPW>(buf, L, L, twid);
+    for (int i = threadIdx.x; i < L * CPW; i += kBlock) {
+        const int ky = i / CPW, c = i - ky * CPW;
+        col[(int64_t)ky * L + c] = buf[c * L + ky];
+    }
 }
 
 // The spectra of mode (ky, kx) from its transformed channels (density, jx,
