@@ -444,45 +444,62 @@ k2_dft_cols(int L, const double2 *__restrict__ X_all, const double *__restrict__
 }
 
 // Power-of-two L: the same transforms as radix-2 FFTs, O(L^2 log L) per
-// sample instead of O(L^3).  One line of L complex values per workgroup in
-// LDS, loaded in bit-reversed order, then log2 L butterfly stages with the
-// twiddles e^{-2 pi i k / L} (k = j L / len for the stage of length len).
-__device__ __forceinline__ void k2_fft_line(double2 *buf, int L, const double *__restrict__ twid) {
-    for (int len = 2; len <= L; len <<= 1) {
-        const int half = len >> 1, step = L / len;
-        for (int b = threadIdx.x; b < L / 2; b += kBlock) {
-            const int grp = b / half, j = b - grp * half;
-            const int i0 = grp * len + j, i1 = i0 + half;
-            const double c = twid[j * step], sn = twid[L + j * step];
-            const double2 u = buf[i0], v = buf[i1];
-            const double tr = v.x * c + v.y * sn, ti = v.y * c - v.x * sn;  // v e^{-i theta}
-            buf[i0] = make_double2(u.x + tr, u.y + ti);
-            buf[i1] = make_double2(u.x - tr, u.y - ti);
+// sample instead of O(L^3).  One line of L complex values in LDS, loaded in
+// bit-reversed order, then the log2 L butterfly stages of length len = 2,
+// 4, ..., L with the twiddles e^{-2 pi i k / L} (k = j L / len).  Two
+// consecutive stages run together on groups of four values held in
+// registers (each value goes through the same two butterflies, with the
+// same twiddles, as in two separate stages): half the barriers and LDS
+// round trips; an odd count starts with one single stage.
+__device__ __forceinline__ void k2_bfly(double2 &u, double2 &v, double c, double sn) {
+    const double tr = v.x * c + v.y * sn, ti = v.y * c - v.x * sn;  // v e^{-i theta}
+    v = make_double2(u.x - tr, u.y - ti);
+    u = make_double2(u.x + tr, u.y + ti);
+}
+
+// NL lines of L values side by side (line l at buf + l * stride), one
+// barrier per pass for all of them.
+template <int NL>
+__device__ __forceinline__ void k2_fft_lines(double2 *buf, int stride, int L, const double *__restrict__ twid) {
+    int len = 2;
+    if (__builtin_ctz((unsigned)L) & 1) {  // odd number of stages: len = 2 alone
+        const int hl = L >> 1;
+        for (int b = threadIdx.x; b < NL * hl; b += kBlock) {
+            const int line = b / hl, i0 = 2 * (b - line * hl);
+            double2 *ln = buf + line * stride;
+            double2 u = ln[i0], v = ln[i0 + 1];
+            k2_bfly(u, v, twid[0], twid[L]);
+            ln[i0] = u;
+            ln[i0 + 1] = v;
+        }
+        __syncthreads();
+        len = 4;
+    }
+    const int ql = L >> 2;
+    for (; len < L; len <<= 2) {  // stages len and 2 len
+        const int half = len >> 1, sa = L / len, sb = sa >> 1;
+        for (int b = threadIdx.x; b < NL * ql; b += kBlock) {
+            const int line = b / ql, g = b - line * ql;
+            const int grp = g / half, j = g - grp * half;
+            const int i0 = grp * 2 * len + j;
+            double2 *ln = buf + line * stride;
+            double2 a = ln[i0], bb = ln[i0 + half], c = ln[i0 + len], d = ln[i0 + len + half];
+            const double c1 = twid[j * sa], s1 = twid[L + j * sa];
+            k2_bfly(a, bb, c1, s1);
+            k2_bfly(c, d, c1, s1);
+            k2_bfly(a, c, twid[j * sb], twid[L + j * sb]);
+            k2_bfly(bb, d, twid[(j + half) * sb], twid[L + (j + half) * sb]);
+            ln[i0] = a;
+            ln[i0 + half] = bb;
+            ln[i0 + len] = c;
+            ln[i0 + len + half] = d;
         }
         __syncthreads();
     }
 }
 
-// The same butterflies on NL lines of L values side by side (line l at
-// buf + l * stride), one barrier per stage for all of them.
-template <int NL>
-__device__ __forceinline__ void k2_fft_lines(double2 *buf, int stride, int L, const double *__restrict__ twid) {
-    const int hl = L >> 1;
-    for (int len = 2; len <= L; len <<= 1) {
-        const int half = len >> 1, step = L / len;
-        for (int b = threadIdx.x; b < NL * hl; b += kBlock) {
-            const int line = b / hl, bb = b - line * hl;
-            const int grp = bb / half, j = bb - grp * half;
-            const int i0 = grp * len + j, i1 = i0 + half;
-            double2 *ln = buf + line * stride;
-            const double c = twid[j * step], sn = twid[L + j * step];
-            const double2 u = ln[i0], v = ln[i1];
-            const double tr = v.x * c + v.y * sn, ti = v.y * c - v.x * sn;  // v e^{-i theta}
-            ln[i0] = make_double2(u.x + tr, u.y + ti);
-            ln[i1] = make_double2(u.x - tr, u.y - ti);
-        }
-        __syncthreads();
-    }
+__device__ __forceinline__ void k2_fft_line(double2 *buf, int L, const double *__restrict__ twid) {
+    k2_fft_lines<1>(buf, L, L, twid);
 }
 
 // Power-of-two L <= kK2LinesMaxL: the density deviation and momentum of the
