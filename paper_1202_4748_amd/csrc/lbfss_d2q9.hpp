@@ -446,56 +446,61 @@ k2_dft_cols(int L, const double2 *__restrict__ X_all, const double *__restrict__
 // Power-of-two L: the same transforms as radix-2 FFTs, O(L^2 log L) per
 // sample instead of O(L^3).  One line of L complex values in LDS, loaded in
 // bit-reversed order, then the log2 L butterfly stages of length len = 2,
-// 4, ..., L with the twiddles e^{-2 pi i k / L} (k = j L / len).  Two
-// consecutive stages run together on groups of four values held in
-// registers (each value goes through the same two butterflies, with the
-// same twiddles, as in two separate stages): half the barriers and LDS
-// round trips; an odd count starts with one single stage.
+// 4, ..., L with the twiddles e^{-2 pi i k / L} (k = j L / len).  Up to three
+// consecutive stages run together on groups of 2^M values held in registers:
+// each value goes through the same butterflies, with the same twiddles, as
+// in separate stages, with a barrier and an LDS round trip per pass instead
+// of per stage.
 __device__ __forceinline__ void k2_bfly(double2 &u, double2 &v, double c, double sn) {
     const double tr = v.x * c + v.y * sn, ti = v.y * c - v.x * sn;  // v e^{-i theta}
     v = make_double2(u.x - tr, u.y - ti);
     u = make_double2(u.x + tr, u.y + ti);
 }
 
+// Stages len, 2 len, ..., 2^(M-1) len on NL lines (line l at buf + l * stride):
+// group g holds the values e_t = base + t half (half = len / 2, t < 2^M), and
+// stage k pairs e_t with e_(t + 2^k) (bit k of t clear) at twiddle
+// (j + (t mod 2^k) half) L / (2^k len), j = g mod half.
+template <int NL, int M>
+__device__ __forceinline__ void k2_fft_pass(double2 *buf, int stride, int L, int len,
+                                            const double *__restrict__ twid) {
+    constexpr int G = 1 << M;
+    const int half = len >> 1, ng = L >> M;
+    for (int b = threadIdx.x; b < NL * ng; b += kBlock) {
+        const int line = b / ng, g = b - line * ng;
+        const int grp = g / half, j = g - grp * half;
+        double2 *ln = buf + line * stride + grp * (half << M) + j;
+        double2 e[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) e[t] = ln[t * half];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int st = L / (len << k);
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                if ((t >> k) & 1) continue;
+                const int tw = (j + (t & ((1 << k) - 1)) * half) * st;
+                k2_bfly(e[t], e[t + (1 << k)], twid[tw], twid[L + tw]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t) ln[t * half] = e[t];
+    }
+    __syncthreads();
+}
+
 // NL lines of L values side by side (line l at buf + l * stride), one
-// barrier per pass for all of them.
+// barrier per pass for all of them.  Three stages per pass where the groups
+// of eight still give every thread one (2048-point lines, the batches'
+// twelve-line column passes), else two (a single 256-point line: 32 groups
+// of eight would leave seven threads in eight idle).
 template <int NL>
 __device__ __forceinline__ void k2_fft_lines(double2 *buf, int stride, int L, const double *__restrict__ twid) {
-    int len = 2;
-    if (__builtin_ctz((unsigned)L) & 1) {  // odd number of stages: len = 2 alone
-        const int hl = L >> 1;
-        for (int b = threadIdx.x; b < NL * hl; b += kBlock) {
-            const int line = b / hl, i0 = 2 * (b - line * hl);
-            double2 *ln = buf + line * stride;
-            double2 u = ln[i0], v = ln[i0 + 1];
-            k2_bfly(u, v, twid[0], twid[L]);
-            ln[i0] = u;
-            ln[i0 + 1] = v;
-        }
-        __syncthreads();
-        len = 4;
-    }
-    const int ql = L >> 2;
-    for (; len < L; len <<= 2) {  // stages len and 2 len
-        const int half = len >> 1, sa = L / len, sb = sa >> 1;
-        for (int b = threadIdx.x; b < NL * ql; b += kBlock) {
-            const int line = b / ql, g = b - line * ql;
-            const int grp = g / half, j = g - grp * half;
-            const int i0 = grp * 2 * len + j;
-            double2 *ln = buf + line * stride;
-            double2 a = ln[i0], bb = ln[i0 + half], c = ln[i0 + len], d = ln[i0 + len + half];
-            const double c1 = twid[j * sa], s1 = twid[L + j * sa];
-            k2_bfly(a, bb, c1, s1);
-            k2_bfly(c, d, c1, s1);
-            k2_bfly(a, c, twid[j * sb], twid[L + j * sb]);
-            k2_bfly(bb, d, twid[(j + half) * sb], twid[L + (j + half) * sb]);
-            ln[i0] = a;
-            ln[i0 + half] = bb;
-            ln[i0 + len] = c;
-            ln[i0 + len + half] = d;
-        }
-        __syncthreads();
-    }
+    int len = 2, left = __builtin_ctz((unsigned)L);
+    if (NL * L >= 8 * kBlock)
+        for (; left >= 3; left -= 3, len <<= 3) k2_fft_pass<NL, 3>(buf, stride, L, len, twid);
+    for (; left >= 2; left -= 2, len <<= 2) k2_fft_pass<NL, 2>(buf, stride, L, len, twid);
+    if (left == 1) k2_fft_pass<NL, 1>(buf, stride, L, len, twid);
 }
 
 __device__ __forceinline__ void k2_fft_line(double2 *buf, int L, const double *__restrict__ twid) {
