@@ -1662,24 +1662,31 @@ int lb2_step(lb2_sim *s, int64_t n) {
             const bool pow2 = (s->L & (s->L - 1)) == 0;
             int logL = 0;
             while ((1 << logL) < s->L) ++logL;
-            // batches: three lines per workgroup and no snapshot array (fewer,
-            // fuller workgroups; the same values as the passes below, which
-            // keep three times the workgroups for one latency-bound lattice)
-            if (pow2 && s->L <= kK2LinesMaxL && s->nrep > 1) {
+            // power-of-two L <= 1024: the density and momentum formed straight
+            // into the row transforms (no snapshot array), three lines per
+            // workgroup; the columns of a batch four adjacent kx per workgroup
+            // (L <= 256) with the spectra added in the same pass, those of one
+            // lattice one line per workgroup (three times the workgroups for
+            // its latency), then the spectra
+            if (pow2 && s->L <= kK2LinesMaxL) {
                 const bool small = s->L <= 256;  // LDS lines sized for L = 256
                 hipLaunchKernelGGL(small ? k2_snap_fft_rows<256> : k2_snap_fft_rows<kK2LinesMaxL>,
                                    dim3((unsigned)s->L, R), dim3(kBlock), 0, s->stream, s->L, logL,
                                    (const float *)s->pop[cur ^ 1], (const double *)s->d_twid, s->d_X);
-                // columns: four adjacent kx per workgroup up to L = 256 (48 KB of
-                // LDS lines), one above, the spectra accumulated in the same pass
-                if (small)
+                if (s->nrep == 1) {
+                    hipLaunchKernelGGL(k2_fft_cols<1>, dim3(lines, R), dim3(kBlock), 0, s->stream, s->L, logL,
+                                       s->d_X, (const double *)s->d_twid);
+                    hipLaunchKernelGGL(k2_spec_acc, dim3(nb, R), dim3(kBlock), 0, s->stream, s->L,
+                                       (const double2 *)s->d_X, s->d_acc);
+                } else if (small) {
                     hipLaunchKernelGGL((k2_fft_cols3_acc<256, 4>), dim3((unsigned)s->L / 4, R), dim3(kBlock), 0,
                                        s->stream, s->L, logL, (const double2 *)s->d_X, (const double *)s->d_twid,
                                        s->d_acc);
-                else
+                } else {
                     hipLaunchKernelGGL((k2_fft_cols3_acc<kK2LinesMaxL, 1>), dim3((unsigned)s->L, R), dim3(kBlock), 0,
                                        s->stream, s->L, logL, (const double2 *)s->d_X, (const double *)s->d_twid,
                                        s->d_acc);
+                }
                 s->n_samples += 1;
                 continue;
             }
@@ -1688,15 +1695,12 @@ int lb2_step(lb2_sim *s, int64_t n) {
             if (pow2) {  // FFTs
                 hipLaunchKernelGGL(k2_fft_rows, dim3(lines, R), dim3(kBlock), 0, s->stream, s->L, logL,
                                    (const double *)s->d_snap, (const double *)s->d_twid, s->d_X);
-                // L = 2048: two adjacent columns per workgroup (rows read as 32
-                // bytes; 64 KB of LDS, two workgroups per CU): 6% faster whole
-                // steps than one, four (one workgroup per CU) 4%
-                if (s->L > kK2LinesMaxL)
-                    hipLaunchKernelGGL(k2_fft_cols<2>, dim3(lines / 2, R), dim3(kBlock), 0, s->stream, s->L, logL,
-                                       s->d_X, (const double *)s->d_twid);
-                else
-                    hipLaunchKernelGGL(k2_fft_cols<1>, dim3(lines, R), dim3(kBlock), 0, s->stream, s->L, logL,
-                                       s->d_X, (const double *)s->d_twid);
+                // L = 2048 (the only power of two left here): two adjacent
+                // columns per workgroup (rows read as 32 bytes; 64 KB of LDS,
+                // two workgroups per CU): 6% faster whole steps than one, four
+                // (one workgroup per CU) 4%
+                hipLaunchKernelGGL(k2_fft_cols<2>, dim3(lines / 2, R), dim3(kBlock), 0, s->stream, s->L, logL,
+                                   s->d_X, (const double *)s->d_twid);
                 hipLaunchKernelGGL(k2_spec_acc, dim3(nb, R), dim3(kBlock), 0, s->stream, s->L, (const double2 *)s->d_X,
                                    s->d_acc);
             } else {
