@@ -199,10 +199,10 @@ typedef struct lb_sim lb_sim; /* opaque, owned by the library */
  * (owned by the library until lb_destroy); p is read during the call only.
  * Initial plan: LB_KERNEL_ROWS where every L allows it (else FUSED, or SPLIT
  * with LB_EQ_PRESSURE); when the largest L is at least 256 (FP32) on 64 x 8
- * tiles in four z slabs, from 128 to 255 (FP32) on 64 x 4 tiles in three,
- * from 128 (FP16) on 64 x 8 tiles in six, from 128 (LB_EQ_PRESSURE) on 64 x 8
- * tiles in eight, else on 32 x 8 tiles; direct launches (lb_set_plan and
- * lb_tune change it; results do not depend on it).
+ * tiles in four z slabs (six from L = 512), from 128 to 255 (FP32) on 64 x 4
+ * tiles in three, from 128 (FP16) on 64 x 8 tiles in six, from 128
+ * (LB_EQ_PRESSURE) on 64 x 8 tiles in eight, else on 32 x 8 tiles; direct
+ * launches (lb_set_plan and lb_tune change it; results do not depend on it).
  * Errors: LB_EINVAL for L < 4, L > 1024, tau <= 1/2, kT < 0, kappa < 0,
  * b < 0, rho_c <= 0, init_sigma < 0, bad storage, flags, sample_every < 0,
  * n_levels < 0 or series_capacity < 0; LB_ENOMEM; LB_EDEVICE. */

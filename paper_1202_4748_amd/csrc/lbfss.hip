@@ -857,18 +857,21 @@ int create_impl(int n, const int *L, const lb_params *p, const uint64_t *seeds, 
     if (rows_ok(s)) {
         def.kernel = LB_KERNEL_ROWS;
         // large lattices, wider source rows: FP32 from L = 256 on 64 x 8
-        // tiles in four z slabs (L = 256: 512 tiles, one round of two
-        // 512-thread workgroups per CU; a quarter fewer staged bytes per site than
-        // 64 x 4, 9% faster), below on 64 x 4 tiles in three (768 tiles at
-        // L = 256, three workgroups per CU); FP16 on 64 x 8 tiles in six
-        // (64 x 4 measured 5%, 32 x 8 15% slower)
+        // tiles (a quarter fewer staged bytes per site than 64 x 4; 9% faster
+        // at 256^3), in four z slabs while one slab layer of tiles cannot fill
+        // a round of two 512-thread workgroups per CU (L = 256: 512 tiles, one
+        // round), else in six (L = 512: 7% faster than four); below L = 256 on
+        // 64 x 4 tiles in three (three workgroups per CU); FP16 on 64 x 8
+        // tiles in six (64 x 4 measured 5%, 32 x 8 15% slower)
         int maxL = 0;
         for (const auto &d : s->hdesc) maxL = std::max(maxL, d.L);
         if (maxL >= 128) {
             const bool wide = s->storage == LB_FP16 || maxL >= 256;
+            const int64_t layer = ceil_div(maxL, 64) * ceil_div(maxL, 8);
             def.tile_x = 64;
             def.tile_y = wide ? 8 : 4;
-            def.tile_z = s->storage == LB_FP16 ? (maxL + 5) / 6 : (wide ? (maxL + 3) / 4 : (maxL + 2) / 3);
+            def.tile_z = !wide ? (maxL + 2) / 3
+                               : (s->storage == LB_FP16 || layer >= 512 ? (maxL + 5) / 6 : (maxL + 3) / 4);
             // the paper's model (k_meq_staged) on 64 x 8 tiles (512 threads,
             // 62.6 KB of LDS, two workgroups per CU) in eight slabs: as fast
             // as 64 x 4 tiles with 17% less HBM traffic (reads 1.13x against
