@@ -110,6 +110,41 @@ k_sk3_yz(int L, int KX, const double2 *__restrict__ in, double2 *__restrict__ ou
 // C[kz][ky][kx] = |X|^2 / (N rho0^2).
 inline int sk3_fft_tile(int L) { return std::min(2048 / L, 64); }
 
+// Stages m, 2m, ..., 2^(M-1) m of the tile (element n of column j at
+// T[n KT + j]): group g of column j holds e_t = base + t half (half = m / 2,
+// t < 2^M), stage k pairs e_t with e_(t + 2^k) (bit k of t clear) at twiddle
+// index (q + (t mod 2^k) half) L / (2^k m), q = group mod half.
+template <int M>
+__device__ __forceinline__ void sk3_fft_pass(double2 *T, int L, int KT, int m, const double *cs, const double *sn) {
+    constexpr int G = 1 << M;
+    const int half = m >> 1, ng = (L >> M) * KT;
+    for (int b = threadIdx.x; b < ng; b += kBlock) {
+        const int j = b % KT, bb = b / KT;
+        const int grp = bb / half, q = bb - grp * half;
+        double2 *col = T + (grp * (half << M) + q) * KT + j;
+        double2 e[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) e[t] = col[t * half * KT];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int step = L / (m << k);
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                if ((t >> k) & 1) continue;
+                const int w = (q + (t & ((1 << k) - 1)) * half) * step;
+                const double wr = cs[w], wi = -sn[w];
+                const double2 u = e[t], v = e[t + (1 << k)];
+                const double tr = v.x * wr - v.y * wi, ti = v.x * wi + v.y * wr;
+                e[t] = make_double2(u.x + tr, u.y + ti);
+                e[t + (1 << k)] = make_double2(u.x - tr, u.y - ti);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t) col[t * half * KT] = e[t];
+    }
+    __syncthreads();
+}
+
 template <int AXIS>
 __global__ void __launch_bounds__(kBlock)
 k_sk3_fft(int L, int log2L, int KT, const float *__restrict__ drho, const double2 *__restrict__ in,
@@ -143,20 +178,15 @@ k_sk3_fft(int L, int log2L, int KT, const float *__restrict__ drho, const double
         sn[x] = twid[L + x];
     }
     __syncthreads();
-    for (int m = 2; m <= L; m <<= 1) {
-        const int half = m >> 1, step = L / m;
-        for (int b = threadIdx.x; b < (L / 2) * KT; b += kBlock) {
-            const int j = b % KT, bb = b / KT;
-            const int g = bb / half, q = bb - g * half;
-            const int i1 = (g * m + q) * KT + j, i2 = i1 + half * KT;
-            const double wr = cs[q * step], wi = -sn[q * step];
-            const double2 u = T[i1], v = T[i2];
-            const double tr = v.x * wr - v.y * wi, ti = v.x * wi + v.y * wr;
-            T[i1] = make_double2(u.x + tr, u.y + ti);
-            T[i2] = make_double2(u.x - tr, u.y - ti);
-        }
-        __syncthreads();
-    }
+    // stages m = 2, 4, ..., L, up to three per pass on groups of 2^M values of
+    // one column held in registers (each value through the same butterflies
+    // with the same twiddles as stage by stage); three where the groups still
+    // give every thread one
+    int m = 2, left = log2L;
+    if ((L >> 3) * KT >= kBlock)
+        for (; left >= 3; left -= 3, m <<= 3) sk3_fft_pass<3>(T, L, KT, m, cs, sn);
+    for (; left >= 2; left -= 2, m <<= 2) sk3_fft_pass<2>(T, L, KT, m, cs, sn);
+    if (left == 1) sk3_fft_pass<1>(T, L, KT, m, cs, sn);
     double scale = 0.0;
     if (AXIS == 2) {
         const double rho0 = gl[1];
