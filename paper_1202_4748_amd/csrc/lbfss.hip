@@ -102,7 +102,8 @@ struct lb_sim {
     int64_t *d_cum_rows = nullptr, *d_cum_cols = nullptr, *d_cum_bx = nullptr, *d_cum_by = nullptr,
             *d_cum_bz = nullptr, *d_cum_planes = nullptr, *d_cum_direct = nullptr, *d_cum_sk = nullptr;
     int64_t n_rows = 0, n_cols = 0, n_bx = 0, n_by = 0, n_bz = 0, n_planes = 0, n_direct = 0, n_sk = 0;
-    std::vector<int64_t *> d_cum_coarse;
+    std::vector<int64_t *> d_cum_coarse;      // per coarsening launch: workgroups per replica, prefix sums
+    std::vector<CoarsenGroup *> d_coarse_grp; // per coarsening launch: the levels of each replica
     std::vector<int64_t> n_coarse;
     int max_nlev = 0;
     BoxChunk *d_chunks = nullptr;
@@ -392,11 +393,9 @@ void enqueue_sample_rest(lb_sim *s, int koff, bool sk3) {
         hipLaunchKernelGGL(k_box_z, dim3((unsigned)ceil_div(s->n_bz, kBlock)), dim3(kBlock), 0, s->stream,
                            s->d_sd, s->d_cum_bz, s->nrep, s->d_ws);
     }
-    for (int lev = s->max_nlev - 2; lev >= 0; --lev) {
-        if (s->n_coarse[lev] == 0) continue;
-        hipLaunchKernelGGL(k_coarsen, dim3((unsigned)ceil_div(s->n_coarse[lev], kBlock)), dim3(kBlock), 0,
-                           s->stream, s->d_sd, s->d_cum_coarse[lev], s->nrep, lev, s->d_ws);
-    }
+    for (size_t j = 0; j < s->n_coarse.size(); ++j)
+        hipLaunchKernelGGL(k_coarsen_cube, dim3((unsigned)s->n_coarse[j]), dim3(kBlock), 0, s->stream, s->d_sd,
+                           s->d_cum_coarse[j], s->d_coarse_grp[j], s->nrep, s->d_ws);
     if (s->n_chunks > 0)
         hipLaunchKernelGGL(k_level_partials, dim3(s->n_chunks), dim3(kBlock), 0, s->stream, s->d_sd, s->d_chunks,
                            (const float *)s->d_snap, s->d_ws, s->d_parts, s->d_hist);
@@ -492,7 +491,7 @@ int build_sampling(lb_sim *s) {
     s->max_nlev = 0;
     for (int r = 0; r < s->nrep; ++r)
         s->max_nlev = std::max<int>(s->max_nlev, (int)block_levels(s->L[r], s->P[r].n_levels).size());
-    std::vector<std::vector<int64_t>> cum_coarse(std::max(s->max_nlev - 1, 0), std::vector<int64_t>{0});
+    std::vector<std::vector<CoarsenGroup>> coarse_of(s->nrep);  // per replica, per launch
     for (int r = 0; r < s->nrep; ++r) {
         const int L = s->L[r];
         SampDesc d;
@@ -575,13 +574,11 @@ int build_sampling(lb_sim *s) {
         cum_bx.push_back(cum_bx.back() + (separable ? LL * d.nb : 0));
         cum_by.push_back(cum_by.back() + (separable ? (int64_t)L * d.nb * d.nb : 0));
         cum_bz.push_back(cum_bz.back() + (separable ? (int64_t)d.nb * d.nb * d.nb : 0));
-        for (int l = 0; l + 1 < s->max_nlev; ++l) {
-            int64_t n = 0;
-            if (l < d.base_lev) {  // coarser than the stored base: from the next finer level
-                const int64_t nbl = L / lev[l];
-                n = nbl * nbl * nbl;
-            }
-            cum_coarse[l].push_back(cum_coarse[l].back() + n);
+        // levels coarser than the stored base, up to three per launch
+        for (int f = d.base_lev; f > 0;) {
+            const int nl = std::min(3, f);
+            coarse_of[r].push_back(CoarsenGroup{f, nl});
+            f -= nl;
         }
         s->hsd.push_back(d);
     }
@@ -604,11 +601,23 @@ int build_sampling(lb_sim *s) {
     if ((rc = upload(s, &s->d_cum_bx, cum_bx))) return rc;
     if ((rc = upload(s, &s->d_cum_by, cum_by))) return rc;
     if ((rc = upload(s, &s->d_cum_bz, cum_bz))) return rc;
-    s->d_cum_coarse.assign(cum_coarse.size(), nullptr);
-    s->n_coarse.assign(cum_coarse.size(), 0);
-    for (size_t l = 0; l < cum_coarse.size(); ++l) {
-        if ((rc = upload(s, &s->d_cum_coarse[l], cum_coarse[l]))) return rc;
-        s->n_coarse[l] = cum_coarse[l].back();
+    size_t n_launch = 0;
+    for (const auto &c : coarse_of) n_launch = std::max(n_launch, c.size());
+    s->d_cum_coarse.assign(n_launch, nullptr);
+    s->d_coarse_grp.assign(n_launch, nullptr);
+    s->n_coarse.assign(n_launch, 0);
+    for (size_t j = 0; j < n_launch; ++j) {
+        std::vector<int64_t> cum{0};
+        std::vector<CoarsenGroup> grp;
+        for (int r = 0; r < s->nrep; ++r) {
+            const CoarsenGroup cg = j < coarse_of[r].size() ? coarse_of[r][j] : CoarsenGroup{0, 0};
+            const int64_t nt = cg.nl > 0 ? (int64_t)2 << (cg.fine - cg.nl) : 0;  // top-level boxes per axis
+            grp.push_back(cg);
+            cum.push_back(cum.back() + nt * nt * nt);
+        }
+        if ((rc = upload(s, &s->d_cum_coarse[j], cum))) return rc;
+        if ((rc = upload(s, &s->d_coarse_grp[j], grp))) return rc;
+        s->n_coarse[j] = cum.back();
     }
     if ((rc = upload(s, &s->d_chunks, chunks))) return rc;
     s->n_chunks = (int)chunks.size();

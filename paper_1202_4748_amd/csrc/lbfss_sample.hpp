@@ -64,25 +64,33 @@ __device__ __forceinline__ int find_cum(const int64_t *__restrict__ cum, int nre
     return lo;
 }
 
-// Deterministic FP64 sum over a 256-thread workgroup (fixed tree).
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    sh[threadIdx.x] = v;
-    __syncthreads();
-#pragma unroll
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    const double out = sh[0];
-    __syncthreads();
-    return out;
-}
-
 // Deterministic FP64 sum over one 64-lane wave (fixed butterfly).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
     return v;
+}
+
+// N deterministic FP64 sums over a 256-thread workgroup at once, each by
+// the fixed tree v[t] += v[t + s], s = 128, 64, ..., 1: the two cross-wave
+// halvings in LDS (sh holds N * kBlock doubles), then the wave butterfly,
+// whose lane 0 adds the same pairs in the same order.  The sums are valid
+// in thread 0 only.
+template <int N>
+__device__ __forceinline__ void block_sums(double (&v)[N], double *sh) {
+    static_assert(kBlock == 256, "two cross-wave halvings, then one wave");
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < N; ++q) sh[q * kBlock + t] = v[q];
+    __syncthreads();
+    if (t < 128)
+#pragma unroll
+        for (int q = 0; q < N; ++q) sh[q * kBlock + t] += sh[q * kBlock + t + 128];
+    __syncthreads();
+    if (t < 64)
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] = wave_sum(sh[q * kBlock + t] + sh[q * kBlock + t + 64]);
+    __syncthreads();
 }
 
 // 1. Snapshot of drho and j at every site (pulled populations), FP32.
@@ -118,7 +126,20 @@ k_rows(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nre
     const int L = s.L;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t base = s.site_off + lr * L;
-    for (int x = lane; x < L; x += 64)
+    int x = lane;
+    // four x chunks of the four channels loaded before they are added (same order)
+    for (; x + 192 < L; x += 256) {
+        float t[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) t[u][c] = snap[c * total_sites + base + x + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += (double)t[u][c];
+    }
+    for (; x < L; x += 64)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] += (double)snap[c * total_sites + base + x];
 #pragma unroll
@@ -156,9 +177,18 @@ k_cols(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nre
         const SampDesc &s = sd[r];
         li = g - cum[r];
         const int L = s.L;
-        const int64_t z = li / L, x = li - z * L;
+        const uint32_t zi = (uint32_t)li / (uint32_t)L;  // li < L^2
+        const int64_t z = zi, x = li - (int64_t)zi * L;
         const float *col = snap + s.site_off + x + (int64_t)L * L * z;
         int y = 0;
+        // eight rows of this phase loaded before they are added (same order)
+        for (; y + 31 < L; y += 32) {
+            float t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[u] = col[(int64_t)(y + 4 * u + k) * L];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a += (double)t[u];
+        }
         for (; y + 3 < L; y += 4) a += (double)col[(int64_t)(y + k) * L];
         if (k == 0)
             for (; y < L; ++y) a += (double)col[(int64_t)y * L];
@@ -204,7 +234,7 @@ k_planes(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int n
 // deviation dbar that defines phi.
 __global__ void __launch_bounds__(kBlock)
 k_totals(const SampDesc *__restrict__ sd, const RepDesc *__restrict__ desc, int nrep, double *__restrict__ ws) {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[4 * kBlock];
     const int r = blockIdx.x;
     const SampDesc &s = sd[r];
     const int L = s.L;
@@ -213,8 +243,9 @@ k_totals(const SampDesc *__restrict__ sd, const RepDesc *__restrict__ desc, int 
         const double *P = ws + s.planes_off + (int64_t)(2 + c) * L;
         double a = 0.0;
         for (int k = threadIdx.x; k < L; k += kBlock) a += P[k];
-        tot[c] = block_sum(a, sh);
+        tot[c] = a;
     }
+    block_sums(tot, sh);
     if (threadIdx.x == 0) {
         const double N = (double)L * (double)L * (double)L;
         const double rho_c = (double)desc[r].rho_c;
@@ -237,21 +268,33 @@ k_box_direct(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, i
     if (g >= cum[nrep]) return;
     const int r = find_cum(cum, nrep, g);
     const SampDesc &s = sd[r];
-    const int64_t li = g - cum[r];
     const int L = s.L, Lb = s.lev_L[s.base_lev];
-    const int64_t nbl = L / Lb;
-    const int64_t bz = li / (nbl * nbl), rem = li - bz * nbl * nbl;
-    const int64_t by = rem / nbl, bx = rem - by * nbl;
+    const uint32_t nbl = (uint32_t)(L / Lb);
+    const uint32_t li = (uint32_t)(g - cum[r]);  // < nbl^3 <= 2^27: 32-bit division
+    const uint32_t bzy = li / nbl;
+    const int64_t bx = li - bzy * nbl, bz = bzy / nbl, by = bzy - (uint32_t)bz * nbl;
     const float *src = snap + s.site_off + bx * Lb + (int64_t)L * (by * Lb + (int64_t)L * bz * Lb);
     double a1 = 0.0, a2 = 0.0;
-    for (int dz = 0; dz < Lb; ++dz)
-        for (int dy = 0; dy < Lb; ++dy)
-            for (int dx = 0; dx < Lb; ++dx) {
-                const double v = (double)src[dx + (int64_t)L * (dy + (int64_t)L * dz)];
-                a1 += v;
-                a2 += v * v;
-            }
-    const int64_t cnt = nbl * nbl * nbl;
+    if (Lb == 2) {  // the common case: all eight sites loaded first, then added in order
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = src[(u & 1) + (int64_t)L * (((u >> 1) & 1) + (int64_t)L * (u >> 2))];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double v = (double)t[u];
+            a1 += v;
+            a2 += v * v;
+        }
+    } else {
+        for (int dz = 0; dz < Lb; ++dz)
+            for (int dy = 0; dy < Lb; ++dy)
+                for (int dx = 0; dx < Lb; ++dx) {
+                    const double v = (double)src[dx + (int64_t)L * (dy + (int64_t)L * dz)];
+                    a1 += v;
+                    a2 += v * v;
+                }
+    }
+    const int64_t cnt = (int64_t)nbl * nbl * nbl;
     ws[s.lev_off[s.base_lev] + li] = a1;
     ws[s.lev_off[s.base_lev] + cnt + li] = a2;
 }
@@ -325,32 +368,67 @@ k_box_z(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nr
     ws[dst + cnt + li] = a2;
 }
 
-// 8. Level lev from its finer neighbour lev + 1: each box sums its 8 children.
+// 8. Coarser levels from a stored finer one.  Level l has 2^(l + 1) boxes
+// per axis whatever L is, and a box sums its 8 children (z, then y, then x).
+// One launch forms up to three levels per replica: a workgroup loads a cube
+// of e^3 boxes (e = 2^nl <= 8) of level `fine` into LDS and forms the
+// (e/2)^3, (e/4)^3, ... boxes of the levels fine - 1, ..., fine - nl above
+// it, each written out and kept in LDS for the next.
+struct CoarsenGroup {
+    int32_t fine, nl;  // nl = 0: nothing for this replica in this launch
+};
+
 __global__ void __launch_bounds__(kBlock)
-k_coarsen(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum, int nrep, int lev,
-          double *__restrict__ ws) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= cum[nrep]) return;
+k_coarsen_cube(const SampDesc *__restrict__ sd, const int64_t *__restrict__ cum,
+               const CoarsenGroup *__restrict__ grp, int nrep, double *__restrict__ ws) {
+    __shared__ double cube[2][2][512];  // [buffer][sum of drho, of drho^2][box]
+    const int64_t g = blockIdx.x;
+    if (g >= cum[nrep]) return;  // whole workgroup
     const int r = find_cum(cum, nrep, g);
     const SampDesc &s = sd[r];
-    const int64_t li = g - cum[r];
-    const int64_t nc = s.L / s.lev_L[lev];  // boxes per axis, this level
-    const int64_t nf = 2 * nc;
-    const int64_t bz = li / (nc * nc), rem = li - bz * nc * nc;
-    const int64_t by = rem / nc, bx = rem - by * nc;
-    const double *fine = ws + s.lev_off[lev + 1];
-    const int64_t cntf = nf * nf * nf;
-    double a1 = 0.0, a2 = 0.0;
-    for (int dz = 0; dz < 2; ++dz)
-        for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-                const int64_t src = (2 * bx + dx) + nf * ((2 * by + dy) + nf * (2 * bz + dz));
-                a1 += fine[src];
-                a2 += fine[cntf + src];
-            }
-    const int64_t cnt = nc * nc * nc;
-    ws[s.lev_off[lev] + li] = a1;
-    ws[s.lev_off[lev] + cnt + li] = a2;
+    const CoarsenGroup cg = grp[r];
+    // every edge is a power of two: indices split by shifts (li < 2^27)
+    const uint32_t li = (uint32_t)(g - cum[r]);
+    const int ln = cg.nl, e = 1 << ln;
+    const int lt = cg.fine - cg.nl + 1;  // log2 of the top-level boxes per axis
+    const int64_t cz = li >> (2 * lt), cy = (li >> lt) & ((1u << lt) - 1), cx = li & ((1u << lt) - 1);
+    {
+        const int64_t nf = (int64_t)2 << cg.fine;
+        const double *f1 = ws + s.lev_off[cg.fine], *f2 = f1 + nf * nf * nf;
+        for (int i = threadIdx.x; i < e * e * e; i += kBlock) {
+            const int dz = i >> (2 * ln), dy = (i >> ln) & (e - 1), dx = i & (e - 1);
+            const int64_t src = (cx * e + dx) + nf * ((cy * e + dy) + nf * (cz * e + dz));
+            cube[0][0][i] = f1[src];
+            cube[0][1][i] = f2[src];
+        }
+    }
+    __syncthreads();
+    for (int k = 1; k <= cg.nl; ++k) {
+        const int ef = e >> (k - 1), ec = e >> k;   // this cube's edge at the finer, coarser level
+        const double *a = cube[(k - 1) & 1][0], *b = cube[(k - 1) & 1][1];
+        double *oa = cube[k & 1][0], *ob = cube[k & 1][1];
+        const int lev = cg.fine - k;
+        const int64_t nc = (int64_t)2 << lev;
+        const int lc = ln - k;  // log2 ec
+        for (int i = threadIdx.x; i < ec * ec * ec; i += kBlock) {
+            const int bz = i >> (2 * lc), by = (i >> lc) & (ec - 1), bx = i & (ec - 1);
+            double a1 = 0.0, a2 = 0.0;
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const int src = (2 * bx + dx) + ef * ((2 * by + dy) + ef * (2 * bz + dz));
+                        a1 += a[src];
+                        a2 += b[src];
+                    }
+            oa[i] = a1;
+            ob[i] = a2;
+            const int64_t dst = (cx * ec + bx) + nc * ((cy * ec + by) + nc * (cz * ec + bz));
+            double *out = ws + s.lev_off[lev];
+            out[dst] = a1;
+            out[nc * nc * nc + dst] = a2;
+        }
+        __syncthreads();
+    }
 }
 
 // 9. Partial sums over a chunk of boxes of m, m^2, m^3, m^4, |m|, E, E^2,
@@ -364,7 +442,7 @@ __global__ void __launch_bounds__(kBlock)
 k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ chunks,
                  const float *__restrict__ snap, double *__restrict__ ws, double *__restrict__ parts,
                  unsigned long long *__restrict__ hist) {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kMoments * kBlock];
     __shared__ unsigned int s_hist[kMaxHistBins + 2];
     const BoxChunk c = chunks[blockIdx.x];
     const SampDesc &s = sd[c.rep];
@@ -421,11 +499,10 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
         for (int i = threadIdx.x; i < nbins + 2; i += kBlock)
             if (s_hist[i]) atomicAdd(&hl[i], (unsigned long long)s_hist[i]);
     }
+    block_sums(acc, sh);
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < kMoments; ++q) {
-        const double v = block_sum(acc[q], sh);
-        if (threadIdx.x == 0) parts[(int64_t)blockIdx.x * kMoments + q] = v;
-    }
+        for (int q = 0; q < kMoments; ++q) parts[(int64_t)blockIdx.x * kMoments + q] = acc[q];
 }
 
 // Axis structure factor S_a(k_m) = N^-1 |sum_n P_a(n) e^{-i k_m n}|^2 of phi,
@@ -467,7 +544,7 @@ k_structure_factor(const SampDesc *__restrict__ sd, const int64_t *__restrict__ 
 __global__ void __launch_bounds__(kBlock)
 k_level_reduce(const SampDesc *__restrict__ sd, int max_nlev, double *__restrict__ ws,
                const double *__restrict__ parts, double *__restrict__ acc_all) {
-    __shared__ double sh[kBlock];
+    __shared__ double sh[kMoments * kBlock];
     const int r = blockIdx.x / max_nlev, lev = blockIdx.x - r * max_nlev;
     const SampDesc &s = sd[r];
     if (lev >= s.nlev) return;  // whole workgroup
@@ -475,19 +552,33 @@ k_level_reduce(const SampDesc *__restrict__ sd, int max_nlev, double *__restrict
     // one pass over the chunks for all moments (each moment still adds its
     // chunks in the same order per thread, then the same block sum)
     double v[kMoments] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = threadIdx.x; k < s.chunk_count[lev]; k += kBlock) {
-        const double *pk = parts + (s.chunk_first[lev] + k) * kMoments;
+    const double *p0 = parts + s.chunk_first[lev] * kMoments;
+    const int64_t nch = s.chunk_count[lev];
+    int64_t k = threadIdx.x;
+    // four of this thread's chunks loaded at a time, then added in order
+    for (; k + 3 * kBlock < nch; k += 4 * kBlock) {
+        double t[4][kMoments];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < kMoments; ++q) t[u][q] = p0[(k + u * kBlock) * kMoments + q];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < kMoments; ++q) v[q] += t[u][q];
+    }
+    for (; k < nch; k += kBlock) {
+        const double *pk = p0 + k * kMoments;
 #pragma unroll
         for (int q = 0; q < kMoments; ++q) v[q] += pk[q];
     }
+    block_sums(v, sh);
+    if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < kMoments; ++q) {
-        const double t = block_sum(v[q], sh);
-        if (threadIdx.x == 0) {
-            ws[s.levtot_off + lev * kMoments + q] = t;
-            acc[lev * kMoments + q] += t;
+        for (int q = 0; q < kMoments; ++q) {
+            ws[s.levtot_off + lev * kMoments + q] = v[q];
+            acc[lev * kMoments + q] += v[q];
         }
-    }
 }
 
 // 11. Per replica (one thread each): append a series record, count the sample.
