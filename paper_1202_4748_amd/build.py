@@ -3,6 +3,7 @@ import os
 import re
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -57,6 +58,114 @@ def check_counted_waits(usage):
     return n
 
 
+_LABEL = re.compile(r"^(\.LBB\w+):")
+_LDS_DMA = re.compile(r"^(global|buffer)_load_lds")
+_VMEM = re.compile(r"^(global|buffer|flat|scratch)_(load|store|atomic)")
+_WAIT = re.compile(r"^s_waitcnt\b.*\bvmcnt\((\d+)\)")
+_BRANCH = re.compile(r"^s_c?branch\w*\s+(\.LBB\w+)")
+
+
+def asm_functions(text: str):
+    """{function name: its lines} from device assembly (gfx9 syntax)."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.match(r"^([A-Za-z_][\w.$]*):", line)
+        if m and not line.startswith(".L"):
+            cur = out.setdefault(m.group(1), [])
+            continue
+        if cur is not None and line.startswith(".Lfunc_end"):
+            cur = None
+            continue
+        if cur is not None:
+            cur.append(line)
+    return out
+
+
+def counted_wait_shortfalls(lines):
+    """Counted waits of one kernel that could return early.
+
+    A wait s_waitcnt vmcnt(N) lets the N youngest vector-memory operations
+    of the wave run on; the staged kernels use it to wait for the previous
+    global->LDS copies while the collision's stores still run, which holds
+    only if at least N vector-memory operations were issued after the last
+    copy.  This walks back from each wait with N > 0 along the fall-through
+    path to the last copy and counts them; at a loop header it follows the
+    loop's back edges (the loop's entry takes the vmcnt(0) wait, as no
+    stores precede it).  Returns [(line, N, count)] for every wait whose
+    count is below N, and the number of waits checked."""
+    ins, labels = [], {}
+    for raw in lines:
+        t = raw.split(";")[0].strip()
+        if not t:
+            continue
+        m = _LABEL.match(t)
+        if m:
+            labels[m.group(1)] = len(ins)
+            ins.append(("label", m.group(1), raw))
+            continue
+        if t.startswith("."):
+            continue
+        op = t.split()[0]
+        if _LDS_DMA.match(op):
+            ins.append(("copy", None, raw))
+        elif _VMEM.match(op):
+            ins.append(("vmem", None, raw))
+        elif _WAIT.match(t):
+            ins.append(("wait", int(_WAIT.match(t).group(1)), raw))
+        elif _BRANCH.match(t):
+            ins.append(("branch", _BRANCH.match(t).group(1), raw))
+        else:
+            ins.append(("other", None, raw))
+    back = {}
+    for i, (k, a, _) in enumerate(ins):
+        if k == "branch" and a in labels and labels[a] < i:
+            back.setdefault(a, []).append(i)
+
+    def younger(i, seen):
+        n, j = 0, i - 1
+        while j >= 0:
+            k, a, _ = ins[j]
+            if k == "copy":
+                return n
+            if k == "vmem":
+                n += 1
+            if k == "label" and a in back:
+                if a in seen:
+                    return None
+                counts = [younger(b, seen | {a}) for b in back[a]]
+                counts = [c for c in counts if c is not None]
+                return n + min(counts) if counts else None
+            j -= 1
+        return None  # no copy before it: not a counted wait
+
+    bad, checked = [], 0
+    for i, (k, a, raw) in enumerate(ins):
+        if k == "wait" and a > 0:
+            c = younger(i, frozenset())
+            if c is None:
+                continue
+            checked += 1
+            if c < a:
+                bad.append((raw.strip(), a, c))
+    return bad, checked
+
+
+def check_counted_wait_order(asm: str):
+    """Raise if a staged kernel's counted wait could let a copy it waits for
+    still run (stores merged, moved before the copies or taken out)."""
+    funcs = {k: v for k, v in asm_functions(asm).items() if any(n in k for n in COUNTED_WAIT_KERNELS)}
+    if not funcs:
+        raise RuntimeError("no staged kernels in the device assembly")
+    problems, total = [], 0
+    for name, lines in funcs.items():
+        bad, checked = counted_wait_shortfalls(lines)
+        total += checked
+        problems += [f"{name}: {w} with {c} younger operations" for w, _, c in bad]
+    if problems:
+        raise RuntimeError("counted waits without enough younger operations: " + "; ".join(problems[:5]))
+    return total
+
+
 # staged instances the host launches on large lattices and the waves per
 # SIMD each must keep: two 512-thread workgroups per CU on 64 x 8 tiles (the
 # FP32 snapshot instance is not launched there: sample steps of those plans
@@ -95,15 +204,28 @@ def build(verbose: bool = False, extra=()) -> str:
            os.path.join(ROOT, "include"), "-o", tmp, SRC]
     if verbose:
         print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stderr)
-        raise subprocess.CalledProcessError(r.returncode, cmd)
+    with tempfile.TemporaryDirectory() as td:
+        # the device assembly of the same source and flags, compiled alongside
+        asm_path = os.path.join(td, "lbfss.s")
+        acmd = [hipcc, *[f for f in HIPCC_FLAGS if f != "-shared"], *extra, "--cuda-device-only", "-S", "-I",
+                os.path.join(ROOT, "include"), "-o", asm_path, SRC]
+        pa = subprocess.Popen(acmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        a_out, a_err = pa.communicate()
+        if r.returncode != 0:
+            sys.stderr.write(r.stderr)
+            raise subprocess.CalledProcessError(r.returncode, cmd)
+        if pa.returncode != 0:
+            sys.stderr.write(a_err)
+            raise subprocess.CalledProcessError(pa.returncode, acmd)
+        with open(asm_path) as f:
+            w = check_counted_wait_order(f.read())
     usage = resource_usage(r.stderr)
     n = check_counted_waits(usage)
     m = check_occupancy(usage)
     if verbose:
-        print(f"{n} staged kernel instances without scratch memory, {m} at their occupancy", flush=True)
+        print(f"{n} staged kernel instances without scratch memory, {m} at their occupancy, "
+              f"{w} counted waits behind enough younger operations", flush=True)
     os.replace(tmp, LIB)
     return LIB
 

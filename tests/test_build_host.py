@@ -1,7 +1,8 @@
-"""The build's guard for the staged kernels' counted waits: the compiler's
+"""The build's guards for the staged kernels' counted waits: the compiler's
 resource-usage remarks are parsed, and a staged kernel with scratch memory
 (whose spills would add vector-memory operations the waits do not count)
-fails the build."""
+fails the build, as does one whose device assembly places fewer operations
+after its global->LDS copies than a wait lets run on."""
 import pytest
 
 from paper_1202_4748_amd import build
@@ -49,3 +50,46 @@ def test_occupancy_guard():
         build.check_occupancy(build.resource_usage(_occ_remarks(3)))
     with pytest.raises(RuntimeError, match="no resource-usage remark"):
         build.check_occupancy({})
+
+
+def _staged_asm(stores_after_copy=19, stores_before_copy=0):
+    """A staged kernel's loop as the compiler lays it out: the loop header
+    holds the counted wait (taken when the last iteration stored), the body
+    issues the next plane's copies, then the collision's stores."""
+    body = ["\tglobal_store_dword v1, v2, s[0:1]"] * stores_before_copy
+    body += ["\tglobal_load_lds_dwordx4 v3, s[4:5] offset:16"]
+    body += ["\tglobal_store_dword v1, v2, s[0:1]"] * stores_after_copy
+    return "\n".join([
+        "_ZN5lbfss14k_fused_stagedIfLi64ELi8ELb1ELb0EEEvv:",
+        "\tglobal_load_lds_dwordx4 v3, s[4:5]",
+        ".LBB0_1:                                ; =>This Inner Loop Header: Depth=1",
+        "\ts_cbranch_execz .LBB0_3",
+        "\ts_waitcnt vmcnt(0)",
+        ".LBB0_3:",
+        "\ts_cbranch_execz .LBB0_4",
+        "\ts_waitcnt vmcnt(19)",
+        ".LBB0_4:",
+        "\ts_barrier",
+        *body,
+        "\ts_cbranch_scc1 .LBB0_1",
+        "\ts_endpgm",
+        ".Lfunc_end0:",
+    ]) + "\n"
+
+
+def test_counted_wait_order_guard():
+    """The build reads the device assembly: every vmcnt(19) wait of a staged
+    kernel must follow at least 19 vector-memory operations issued after the
+    last global->LDS copy (here along the loop's back edge).  Stores moved
+    ahead of the copies, or fewer of them (merged), fail the build."""
+    assert build.check_counted_wait_order(_staged_asm()) == 1
+    with pytest.raises(RuntimeError, match="0 younger"):
+        build.check_counted_wait_order(_staged_asm(stores_after_copy=0, stores_before_copy=19))
+    with pytest.raises(RuntimeError, match="18 younger"):
+        build.check_counted_wait_order(_staged_asm(stores_after_copy=18))
+    straight = "\n".join(["_ZN5lbfss12k_meq_stagedILi64ELi8ELb0EEEvv:", "\tglobal_load_lds_dword v3, s[4:5]"]
+                         + ["\tglobal_store_dword v1, v2, s[0:1]"] * 5 + ["\ts_waitcnt vmcnt(19)", ".Lfunc_end1:"])
+    with pytest.raises(RuntimeError, match="5 younger"):
+        build.check_counted_wait_order(straight)
+    with pytest.raises(RuntimeError, match="no staged kernels"):
+        build.check_counted_wait_order("_ZN5lbfss9k_collideIfLb0EEEvv:\n\ts_endpgm\n.Lfunc_end2:\n")
