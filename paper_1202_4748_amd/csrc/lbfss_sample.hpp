@@ -464,17 +464,7 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
     const double *b2 = b1 + cnt;
     const float *sn = snap + s.site_off;
     double acc[kMoments] = {0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < kBoxesPerThread; ++k) {
-        const int64_t i = (int64_t)k * kBlock + threadIdx.x;
-        if (i >= c.count) break;
-        double B1, B2;
-        if (from_snap) {
-            B1 = (double)sn[c.first + i];
-            B2 = B1 * B1;
-        } else {
-            B1 = b1[c.first + i];
-            B2 = b2[c.first + i];
-        }
+    auto add_box = [&](double B1, double B2) __attribute__((always_inline)) {
         const double sphi = (B1 - n * dbar) * inv_rho0;
         const double sphi2 = (B2 - 2.0 * dbar * B1 + n * dbar * dbar) * inv_rho0 * inv_rho0;
         const double m = sphi * inv_n, E = sphi2 * inv_2n;
@@ -491,6 +481,43 @@ k_level_partials(const SampDesc *__restrict__ sd, const BoxChunk *__restrict__ c
             // in range: its bin; below -h (or not a number): nbins; at or above h: nbins + 1
             const int idx = (kf >= 0.0 && kf < (double)nbins) ? (int)kf : (kf >= (double)nbins ? nbins + 1 : nbins);
             atomicAdd(&s_hist[idx], 1u);
+        }
+    };
+    // a full chunk (every chunk of a level but its last): the thread's loads
+    // issued together, eight at a time for the stored levels, then its boxes
+    // added in the same order as the guarded loop below
+    const int64_t i0 = c.first + threadIdx.x;
+    if (c.count == kChunkBoxes && from_snap) {
+        float v[kBoxesPerThread];
+#pragma unroll
+        for (int k = 0; k < kBoxesPerThread; ++k) v[k] = sn[i0 + k * kBlock];
+#pragma unroll
+        for (int k = 0; k < kBoxesPerThread; ++k) {
+            const double B1 = (double)v[k];
+            add_box(B1, B1 * B1);
+        }
+    } else if (c.count == kChunkBoxes) {
+#pragma unroll
+        for (int k0 = 0; k0 < kBoxesPerThread; k0 += 8) {
+            double v1[8], v2[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                v1[k] = b1[i0 + (k0 + k) * kBlock];
+                v2[k] = b2[i0 + (k0 + k) * kBlock];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) add_box(v1[k], v2[k]);
+        }
+    } else {
+        for (int k = 0; k < kBoxesPerThread; ++k) {
+            const int64_t i = (int64_t)k * kBlock + threadIdx.x;
+            if (i >= c.count) break;
+            if (from_snap) {
+                const double B1 = (double)sn[c.first + i];
+                add_box(B1, B1 * B1);
+            } else {
+                add_box(b1[c.first + i], b2[c.first + i]);
+            }
         }
     }
     if (nbins > 0) {
