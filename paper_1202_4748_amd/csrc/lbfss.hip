@@ -425,6 +425,9 @@ void flush_pending(lb_sim *s) {
 
 bool sampling(const lb_sim *s) { return s->sample_every > 0; }
 
+// directly launched steps between two advances of the device step counter
+constexpr int64_t kMaxStepsAhead = 1 << 20;
+
 int64_t graph_period(const lb_sim *s) {
     int64_t P = 2;
     if (sampling(s)) {
@@ -922,9 +925,18 @@ int lb_create_batch(int n, const int *L, const lb_params *p, const uint64_t *see
 int lb_step(lb_sim *s, int64_t n) {
     if (!s || n < 0) return LB_EINVAL;
     const int64_t P = graph_period(s);
+    // steps launched directly since the device step counter was last
+    // advanced: each kernel takes its step as the counter plus this offset,
+    // and one launch advances the counter for all of them
+    int64_t ahead = 0;
+    auto advance = [&]() {
+        if (ahead > 0) hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s->stream, s->d_step, ahead);
+        ahead = 0;
+    };
     while (n > 0) {
         const int G = s->plan.graph_steps;
         if (G > 0 && s->t % P == 0 && n >= G) {
+            advance();  // a graph reads the counter as it starts
             const int gi = s->pending ? 1 : 0;
             if (!s->gexec[gi] || s->g_steps[gi] != G) {
                 int rc = build_graph(s, G, s->pending);
@@ -938,17 +950,18 @@ int lb_step(lb_sim *s, int64_t n) {
         }
         const int cur = (int)(s->t & 1);
         const bool snap = s->pending;
-        enqueue_step(s, cur, 0, snap ? s->d_snap : nullptr);
+        enqueue_step(s, cur, (int)ahead, snap ? s->d_snap : nullptr);
         if (snap) {  // the sample of the state this step started from
             enqueue_reductions(s);
-            enqueue_sample_rest(s, 0, sk3_at(s, s->t));
+            enqueue_sample_rest(s, (int)ahead, sk3_at(s, s->t));
             s->pending = false;
         }
-        hipLaunchKernelGGL(k_add_step, dim3(1), dim3(1), 0, s->stream, s->d_step, (int64_t)1);
+        if (++ahead == kMaxStepsAhead) advance();
         s->t += 1;
         if (sampling(s) && s->t % s->sample_every == 0) s->pending = true;
         n -= 1;
     }
+    advance();
     HIPCHK(hipGetLastError());
     return LB_OK;
 }
