@@ -88,11 +88,12 @@ def counted_wait_shortfalls(lines):
     of the wave run on; the staged kernels use it to wait for the previous
     global->LDS copies while the collision's stores still run, which holds
     only if at least N vector-memory operations were issued after the last
-    copy.  This walks back from each wait with N > 0 along the fall-through
-    path to the last copy and counts them; at a loop header it follows the
-    loop's back edges (the loop's entry takes the vmcnt(0) wait, as no
-    stores precede it).  Returns [(line, N, count)] for every wait whose
-    count is below N, and the number of waits checked."""
+    copy.  Which path reaches a wait depends on run-time state (the waits are
+    chosen by whether the last iteration stored), so this asks, by a forward
+    pass over the control flow, for the largest number of such operations
+    on any path from a copy to each wait with N > 0: stores merged, moved
+    ahead of the copies or dropped lower it on every path.  Returns
+    [(line, N, count)] for each wait below its N, and the number checked."""
     ins, labels = [], {}
     for raw in lines:
         t = raw.split(";")[0].strip()
@@ -114,40 +115,55 @@ def counted_wait_shortfalls(lines):
             ins.append(("wait", int(_WAIT.match(t).group(1)), raw))
         elif _BRANCH.match(t):
             ins.append(("branch", _BRANCH.match(t).group(1), raw))
+        elif op in ("s_endpgm", "s_setpc_b64"):
+            ins.append(("end", None, raw))
         else:
             ins.append(("other", None, raw))
-    back = {}
-    for i, (k, a, _) in enumerate(ins):
-        if k == "branch" and a in labels and labels[a] < i:
-            back.setdefault(a, []).append(i)
+    # basic blocks: they start at labels and after branches
+    starts = sorted({0} | {i for i, x in enumerate(ins) if x[0] == "label"}
+                    | {i + 1 for i, x in enumerate(ins) if x[0] in ("branch", "end") and i + 1 < len(ins)})
+    bounds = list(zip(starts, starts[1:] + [len(ins)]))
+    block_at = {b: k for k, (b, _) in enumerate(bounds)}
+    succ = []
+    for b, e in bounds:
+        out = []
+        last = ins[e - 1] if e > b else None
+        if last and last[0] == "branch" and last[1] in labels:
+            out.append(block_at[labels[last[1]]])
+        uncond = last is not None and ((last[0] == "branch" and last[2].strip().startswith("s_branch "))
+                                       or last[0] == "end")
+        if not uncond and e < len(ins):
+            out.append(block_at[e])
+        succ.append(out)
+    NONE, CAP = -1, 1000  # NONE: no copy on any path yet
 
-    def younger(i, seen):
-        n, j = 0, i - 1
-        while j >= 0:
-            k, a, _ = ins[j]
+    def run(v, b, e, report=None):
+        for i in range(b, e):
+            k, a, raw = ins[i]
             if k == "copy":
-                return n
-            if k == "vmem":
-                n += 1
-            if k == "label" and a in back:
-                if a in seen:
-                    return None
-                counts = [younger(b, seen | {a}) for b in back[a]]
-                counts = [c for c in counts if c is not None]
-                return n + min(counts) if counts else None
-            j -= 1
-        return None  # no copy before it: not a counted wait
+                v = 0
+            elif k == "vmem" and v != NONE:
+                v = min(v + 1, CAP)
+            elif k == "wait" and a > 0 and report is not None and v != NONE:
+                report.append((raw.strip(), a, v))
+        return v
 
-    bad, checked = [], 0
-    for i, (k, a, raw) in enumerate(ins):
-        if k == "wait" and a > 0:
-            c = younger(i, frozenset())
-            if c is None:
-                continue
-            checked += 1
-            if c < a:
-                bad.append((raw.strip(), a, c))
-    return bad, checked
+    entry = [NONE] * len(bounds)
+    work = [0]
+    seen = {0}
+    while work:
+        k = work.pop()
+        b, e = bounds[k]
+        v = run(entry[k], b, e)
+        for s in succ[k]:
+            if v > entry[s] or s not in seen:
+                entry[s] = max(entry[s], v)
+                seen.add(s)
+                work.append(s)
+    waits = []
+    for k, (b, e) in enumerate(bounds):
+        run(entry[k], b, e, waits)
+    return [w for w in waits if w[2] < w[1]], len(waits)
 
 
 def check_counted_wait_order(asm: str):
