@@ -86,14 +86,16 @@ def counted_wait_shortfalls(lines):
 
     A wait s_waitcnt vmcnt(N) lets the N youngest vector-memory operations
     of the wave run on; the staged kernels use it to wait for the previous
-    global->LDS copies while the collision's stores still run, which holds
-    only if at least N vector-memory operations were issued after the last
-    copy.  Which path reaches a wait depends on run-time state (the waits are
-    chosen by whether the last iteration stored), so this asks, by a forward
-    pass over the control flow, for the largest number of such operations
-    on any path from a copy to each wait with N > 0: stores merged, moved
-    ahead of the copies or dropped lower it on every path.  Returns
-    [(line, N, count)] for each wait below its N, and the number checked."""
+    global->LDS copies while the collision's stores (non-temporal, `nt`)
+    still run, which holds only if at least N vector-memory operations were
+    issued after the last copy.  A forward pass over the control flow finds,
+    for each wait with N > 0, the fewest such operations on any path from a
+    copy through collision stores; paths without them are the iterations
+    without a collision, which take the full wait at run time (the waits are
+    chosen by whether the last iteration stored).  Stores merged, moved
+    ahead of the copies or dropped leave such a path below N, or none.
+    Returns [(line, N, count)] for each wait below its N (count 0: no such
+    path), and the number of waits checked."""
     ins, labels = [], {}
     for raw in lines:
         t = raw.split(";")[0].strip()
@@ -110,7 +112,7 @@ def counted_wait_shortfalls(lines):
         if _LDS_DMA.match(op):
             ins.append(("copy", None, raw))
         elif _VMEM.match(op):
-            ins.append(("vmem", None, raw))
+            ins.append(("vmem", "nt" if "_store" in op and re.search(r"\bnt\b", t) else None, raw))
         elif _WAIT.match(t):
             ins.append(("wait", int(_WAIT.match(t).group(1)), raw))
         elif _BRANCH.match(t):
@@ -135,31 +137,38 @@ def counted_wait_shortfalls(lines):
         if not uncond and e < len(ins):
             out.append(block_at[e])
         succ.append(out)
-    NONE, CAP = -1, 1000  # NONE: no copy on any path yet
+    # state at a point: fewest operations since the last copy on a path that
+    # passed collision stores (INF: none), and on a path that passed none
+    INF = 1 << 30
 
     def run(v, b, e, report=None):
+        low, zc = v
         for i in range(b, e):
             k, a, raw = ins[i]
             if k == "copy":
-                v = 0
-            elif k == "vmem" and v != NONE:
-                v = min(v + 1, CAP)
-            elif k == "wait" and a > 0 and report is not None and v != NONE:
-                report.append((raw.strip(), a, v))
-        return v
+                low, zc = INF, 0
+            elif k == "vmem":
+                if a == "nt":
+                    low, zc = min(low + 1, zc + 1), INF
+                else:
+                    low, zc = (low + 1 if low < INF else INF), (zc + 1 if zc < INF else INF)
+            elif k == "wait" and a > 0 and report is not None and (low < INF or zc < INF):
+                report.append((raw.strip(), a, low if low < INF else 0))
+        return low, zc
 
-    entry = [NONE] * len(bounds)
-    work = [0]
-    seen = {0}
+    entry = [(INF, INF)] * len(bounds)
+    work, seen = [0], {0}
     while work:
         k = work.pop()
         b, e = bounds[k]
-        v = run(entry[k], b, e)
-        for s in succ[k]:
-            if v > entry[s] or s not in seen:
-                entry[s] = max(entry[s], v)
-                seen.add(s)
-                work.append(s)
+        low, zc = run(entry[k], b, e)
+        for t in succ[k]:
+            old = entry[t]
+            new = (min(old[0], low), min(old[1], zc))
+            if new != old or t not in seen:
+                entry[t] = new
+                seen.add(t)
+                work.append(t)
     waits = []
     for k, (b, e) in enumerate(bounds):
         run(entry[k], b, e, waits)

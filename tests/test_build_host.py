@@ -56,9 +56,9 @@ def _staged_asm(stores_after_copy=19, stores_before_copy=0):
     """A staged kernel's loop as the compiler lays it out: the loop header
     holds the counted wait (taken when the last iteration stored), the body
     issues the next plane's copies, then the collision's stores."""
-    body = ["\tglobal_store_dword v1, v2, s[0:1]"] * stores_before_copy
+    body = ["\tglobal_store_dword v1, v2, s[0:1] nt"] * stores_before_copy
     body += ["\tglobal_load_lds_dwordx4 v3, s[4:5] offset:16"]
-    body += ["\tglobal_store_dword v1, v2, s[0:1]"] * stores_after_copy
+    body += ["\tglobal_store_dword v1, v2, s[0:1] nt"] * stores_after_copy
     return "\n".join([
         "_ZN5lbfss14k_fused_stagedIfLi64ELi8ELb1ELb0EEEvv:",
         "\tglobal_load_lds_dwordx4 v3, s[4:5]",
@@ -88,8 +88,37 @@ def test_counted_wait_order_guard():
     with pytest.raises(RuntimeError, match="18 younger"):
         build.check_counted_wait_order(_staged_asm(stores_after_copy=18))
     straight = "\n".join(["_ZN5lbfss12k_meq_stagedILi64ELi8ELb0EEEvv:", "\tglobal_load_lds_dword v3, s[4:5]"]
-                         + ["\tglobal_store_dword v1, v2, s[0:1]"] * 5 + ["\ts_waitcnt vmcnt(19)", ".Lfunc_end1:"])
+                         + ["\tglobal_store_dword v1, v2, s[0:1] nt"] * 5 + ["\ts_waitcnt vmcnt(19)", ".Lfunc_end1:"])
     with pytest.raises(RuntimeError, match="5 younger"):
         build.check_counted_wait_order(straight)
     with pytest.raises(RuntimeError, match="no staged kernels"):
         build.check_counted_wait_order("_ZN5lbfss9k_collideIfLb0EEEvv:\n\ts_endpgm\n.Lfunc_end2:\n")
+
+
+def test_counted_wait_guard_takes_any_path():
+    """A path that skips the collision (no stores) reaches the loop header's
+    counted wait too, but at run time it takes the full wait instead: the
+    guard asks for one path from a copy with enough operations, laid out as
+    the compiler does with the copies of the next plane out of line."""
+    asm = "\n".join([
+        "_ZN5lbfss12k_meq_stagedILi64ELi4ELb1EEEvv:",
+        "\tglobal_load_lds_dwordx4 v3, s[4:5]",
+        ".LBB1_1:",
+        "\ts_cbranch_vccz .LBB1_4",
+        "\ts_waitcnt vmcnt(19)",
+        ".LBB1_4:",
+        "\ts_cbranch_scc1 .LBB1_9",      # the copies, out of line
+        ".LBB1_5:",                      # the collision and its stores
+        *["\tglobal_store_dword v1, v2, s[0:1] nt"] * 19,
+        ".LBB1_6:",
+        "\ts_cbranch_scc0 .LBB1_1",
+        "\ts_endpgm",
+        ".LBB1_9:",
+        "\tglobal_load_lds_dwordx4 v3, s[4:5] offset:16",
+        "\ts_cbranch_scc0 .LBB1_5",      # on to the collision
+        "\ts_branch .LBB1_6",            # or past it (no stores)
+        ".Lfunc_end1:",
+    ]) + "\n"
+    assert build.check_counted_wait_order(asm) == 1
+    with pytest.raises(RuntimeError, match="18 younger"):
+        build.check_counted_wait_order(asm.replace("\tglobal_store_dword v1, v2, s[0:1] nt\n", "", 1))
